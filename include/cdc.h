@@ -1,0 +1,166 @@
+/*
+ * cdc.h: chunk-boundary finding for hashless content-defined chunking on
+ * AMD Instinct MI355X (gfx950).  C ABI of libcdc.so.
+ *
+ * The library computes, for a byte buffer, the exclusive end offsets of the
+ * chunks produced by one of the hashless chunkers the paper accelerates:
+ *
+ *   CDC_RAM     RAM (Section 2.1 "RAM"; Section 4.3): the maximum T of the
+ *               first w bytes of a chunk, then the chunk ends right after the
+ *               first later byte >= T.
+ *   CDC_AE      AE-Max (Section 2.1 "AE"; Section 4.3): a target is a byte
+ *               greater than all bytes before it in the chunk; when none of
+ *               the w bytes after a target is greater than it, the chunk ends
+ *               right after those w bytes.
+ *   CDC_MAXP    MAXP (Section 2.1 "MAXP"; Section 4.3): the chunk ends right
+ *               after a byte that is strictly greater than the w bytes before
+ *               it and the w bytes after it.
+ *   CDC_AE_MIN  AE-Min: AE-Max with minima (Section 2.1 "AE").
+ *
+ * Common rules (identical for every chunker): bytes compare as unsigned
+ * values; every chunk is at most max_chunk bytes (a forced cut at
+ * start + max_chunk); every chunk except the last is at least window+1
+ * bytes; the offsets are strictly increasing and the last one is n.
+ * The chunk boundaries are exactly those of the plain byte-by-byte
+ * definition (the paper's accelerated versions generate identical chunks,
+ * Section 6.1).
+ *
+ * Memory and asynchrony.  Every pointer marked "device" is device memory of
+ * the current HIP device (or host memory mapped for device access).  Calls
+ * only validate their scalar arguments, enqueue work on `stream` and return;
+ * results (offsets, counts, per-job status) are written on the device in
+ * stream order and are valid after the caller synchronises the stream.  The
+ * library owns a workspace per (device, stream); it grows only outside
+ * stream capture.  Calls on different streams may run concurrently.
+ */
+#ifndef CDC_H
+#define CDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CDC_RAM = 0,
+    CDC_AE = 1,       /* AE-Max */
+    CDC_MAXP = 2,
+    CDC_AE_MIN = 3
+} cdc_algo;
+
+/* Chunker parameters.  window (w) >= 1; window + 1 <= max_chunk <= 2^31;
+ * flags and reserved must be 0. */
+typedef struct {
+    uint32_t window;
+    uint32_t max_chunk;
+    uint32_t flags;
+    uint32_t reserved;
+} cdc_params;
+
+/* Status codes: 0 on success, negative on error. */
+enum {
+    CDC_OK = 0,
+    CDC_EINVAL = -1,   /* bad argument (null pointer, bad parameters)      */
+    CDC_ENOMEM = -2,   /* workspace too small and cannot grow (capture)    */
+    CDC_EHIP = -3,     /* a HIP call failed; see cdc_last_error()          */
+    CDC_ENOTSUP = -4   /* unsupported device or request                    */
+};
+
+/*
+ * Upper bound on the number of chunk boundaries of an n-byte buffer:
+ * 0 if n == 0, else (n-1)/(window+1) + 1, since every chunk but the last is
+ * at least window+1 bytes.  Returns 0 for invalid parameters.
+ */
+size_t cdc_max_cuts(const cdc_params* p, size_t n);
+
+/*
+ * Chunk one buffer.
+ *   data         device, n bytes, any alignment; read only.
+ *   cut_offsets  device, room for cdc_max_cuts(p, n) uint64 values; receives
+ *                the exclusive chunk ends in increasing order.
+ *   n_cuts       device, one uint64; receives the number of offsets written.
+ *   stream       HIP stream the work is enqueued on (0 = null stream).
+ * Returns CDC_OK once the work is enqueued; CDC_EINVAL for a null pointer
+ * (data may be null when n == 0), bad algo or parameters; CDC_ENOMEM when
+ * the workspace would have to grow during stream capture (call cdc_reserve
+ * first); CDC_EHIP when a launch fails.  Nothing is written on error.
+ * All buffers are owned by the caller.
+ */
+int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
+              size_t n, uint64_t* cut_offsets, uint64_t* n_cuts,
+              hipStream_t stream);
+
+/*
+ * One job of a batch.  data (device, n bytes), cut_offsets (device, room for
+ * cdc_max_cuts entries) and n_cuts (device, one uint64) are owned by the
+ * caller; algo/window/max_chunk as for cdc_chunk.  status is written by the
+ * library: CDC_OK, or CDC_EINVAL for an invalid job (whose *n_cuts is then
+ * set to 0 and whose offsets are not written), or CDC_ENOMEM when the
+ * reserved workspace cannot hold the batch (every job gets it).
+ */
+typedef struct {
+    const uint8_t* data;
+    uint64_t n;
+    uint64_t* cut_offsets;
+    uint64_t* n_cuts;
+    uint32_t algo;
+    uint32_t window;
+    uint32_t max_chunk;
+    int32_t status;
+} cdc_job;
+
+/*
+ * Chunk many independent buffers with one planned set of launches (the
+ * many-file case).  jobs is a DEVICE array of n_jobs descriptors that stays
+ * valid until the work completes; each job's result equals cdc_chunk on that
+ * job alone, with offsets relative to its own data.  The work is sized on
+ * the device from the descriptors, so the sequence can be captured into a
+ * HIP graph and replayed with new descriptor contents, provided
+ * cdc_reserve(stream, ...) reserved room for the largest batch first.
+ * Without a reservation and outside capture, the call reads the
+ * descriptors back (a synchronous copy) to size the workspace.
+ * Returns CDC_OK once enqueued, CDC_EINVAL (jobs null, n_jobs 0),
+ * CDC_ENOMEM (capture without enough reservation) or CDC_EHIP.
+ */
+int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream);
+
+/*
+ * Pre-size the workspace of `stream` for batches of at most max_jobs jobs
+ * holding at most max_total_bytes bytes in total, with windows >= min_window.
+ * Also covers single-buffer calls of up to max_total_bytes bytes.  Call it
+ * outside stream capture.  Returns CDC_OK, CDC_EINVAL or CDC_EHIP.
+ */
+int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
+                uint32_t min_window);
+
+/* Free every workspace owned by the library (after all work completed). */
+void cdc_release(void);
+
+/* Static text for a status code. */
+const char* cdc_status_string(int status);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* cdc_last_error(void);
+
+/*
+ * Tuning knobs (bytes per segment of the segment-parallel chain search and
+ * waves per workgroup).  0 restores the built-in choice.  They change only
+ * speed, never the offsets.  Returns CDC_OK or CDC_EINVAL.
+ */
+int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block);
+
+/*
+ * Diagnostic: synchronise `stream`, return and clear the sticky flags the
+ * kernels raised on it (bit 0: a chain exceeded its planned slot bound,
+ * which indicates a library bug; 0 when nothing was flagged), or CDC_EHIP.
+ */
+int cdc_check_device_errors(hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDC_H */

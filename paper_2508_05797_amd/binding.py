@@ -1,0 +1,129 @@
+"""ctypes binding of libcdc.so: argument marshalling only.
+
+Every step of the chunking runs in the HIP kernels of the library; this
+module passes device pointers, sizes and the current HIP stream of PyTorch.
+It raises if the library has not been built (there is no CPU fallback).
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdc.so")
+
+ALGOS = {"ram": 0, "ae": 1, "maxp": 2, "ae_min": 3}
+STATUS = {0: "CDC_OK", -1: "CDC_EINVAL", -2: "CDC_ENOMEM", -3: "CDC_EHIP",
+          -4: "CDC_ENOTSUP"}
+
+
+class CdcError(RuntimeError):
+    def __init__(self, rc, detail=""):
+        super().__init__("%s (%d) %s" % (STATUS.get(rc, "?"), rc, detail))
+        self.rc = rc
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_uint32), ("max_chunk", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("cut_offsets", ctypes.c_void_p), ("n_cuts", ctypes.c_void_p),
+                ("algo", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("max_chunk", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+_lib = None
+_V, _U32, _U64, _SZ, _I = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64,
+                           ctypes.c_size_t, ctypes.c_int)
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libcdc.so is not built (run paper_2508_05797_amd/build.py); "
+                "there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        L.cdc_max_cuts.restype = _SZ
+        L.cdc_max_cuts.argtypes = [ctypes.POINTER(Params), _SZ]
+        L.cdc_chunk.restype = _I
+        L.cdc_chunk.argtypes = [_I, ctypes.POINTER(Params), _V, _SZ, _V, _V, _V]
+        L.cdc_chunk_batch.restype = _I
+        L.cdc_chunk_batch.argtypes = [_V, _U32, _V]
+        L.cdc_reserve.restype = _I
+        L.cdc_reserve.argtypes = [_V, _SZ, _U32, _U32]
+        L.cdc_release.restype = None
+        L.cdc_release.argtypes = []
+        L.cdc_status_string.restype = ctypes.c_char_p
+        L.cdc_status_string.argtypes = [_I]
+        L.cdc_last_error.restype = ctypes.c_char_p
+        L.cdc_last_error.argtypes = []
+        L.cdc_set_tuning.restype = _I
+        L.cdc_set_tuning.argtypes = [_U64, _U32]
+        L.cdc_check_device_errors.restype = _I
+        L.cdc_check_device_errors.argtypes = [_V]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise CdcError(rc, lib().cdc_last_error().decode())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def algo_id(algo):
+    return ALGOS[algo] if isinstance(algo, str) else int(algo)
+
+
+def max_cuts(n, window):
+    p = Params(window, window + 1, 0, 0)
+    return int(lib().cdc_max_cuts(ctypes.byref(p), n))
+
+
+def chunk_into(data, algo, window, max_chunk, cuts, n_cuts, stream=None):
+    """Enqueue chunking of the uint8 device tensor ``data`` (contiguous) into
+    the int64 device tensors ``cuts`` (>= max_cuts entries) and ``n_cuts``
+    (one entry).  Asynchronous: nothing is synchronised."""
+    assert data.dtype == torch.uint8 and data.is_cuda and data.is_contiguous()
+    n = data.numel()
+    p = Params(window, max_chunk, 0, 0)
+    _check(lib().cdc_chunk(algo_id(algo), ctypes.byref(p),
+                           ctypes.c_void_p(data.data_ptr() if n else 0), n,
+                           ctypes.c_void_p(cuts.data_ptr()),
+                           ctypes.c_void_p(n_cuts.data_ptr()), _stream(stream)))
+
+
+def chunk(data, algo, window, max_chunk, stream=None):
+    """Chunk boundaries (exclusive ends, int64 on the device) of ``data``.
+    Synchronises to read the count."""
+    n = data.numel()
+    cuts = torch.empty(max(1, max_cuts(n, window)), dtype=torch.int64,
+                       device=data.device)
+    n_cuts = torch.empty(1, dtype=torch.int64, device=data.device)
+    chunk_into(data, algo, window, max_chunk, cuts, n_cuts, stream)
+    return cuts[:int(n_cuts.item())]
+
+
+def set_tuning(segment_bytes=0, waves_per_block=0):
+    _check(lib().cdc_set_tuning(segment_bytes, waves_per_block))
+
+
+def device_errors(stream=None):
+    rc = lib().cdc_check_device_errors(_stream(stream))
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def release():
+    lib().cdc_release()

@@ -1,0 +1,298 @@
+// Host runtime and C ABI of libcdc (see include/cdc.h for the contract).
+//
+// The runtime plans a call (segment length, cut slots per segment, MAXP
+// block length), carves the per-(device, stream) workspace and enqueues the
+// kernel sequence.  It never synchronises except to grow a workspace, which
+// it refuses to do while the stream is being captured.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "cdc.h"
+#include "cdc_internal.h"
+
+namespace cdc {
+namespace {
+
+thread_local std::string t_last_error;
+
+void set_error(const char* what, hipError_t e) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    t_last_error = buf;
+}
+
+// Tuning (speed only; never changes the offsets).
+uint64_t g_segment_bytes = 0;
+int g_waves_per_block = 4;
+
+constexpr uint64_t kMinSeg = 64 << 10;
+constexpr uint64_t kMaxSeg = 1ull << 30;
+constexpr uint64_t kTargetSegments = 4096;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Workspace {
+    void* dev = nullptr;
+    size_t cap = 0;
+    // reservation for batches (bytes, jobs, minimum window)
+    size_t res_bytes = 0;
+    uint32_t res_jobs = 0;
+    uint32_t res_min_w = 1;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, uintptr_t>, Workspace> g_ws;
+
+Workspace& workspace_for(hipStream_t st) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return g_ws[{dev, (uintptr_t)st}];
+}
+
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+    return cs != hipStreamCaptureStatusNone;
+}
+
+// Grow the workspace to `need` bytes.  Needs the stream idle: the old buffer
+// may still be in use by work enqueued earlier.
+int ensure(Workspace& ws, size_t need, hipStream_t st) {
+    if (ws.cap >= need) return CDC_OK;
+    if (capturing(st)) {
+        t_last_error = "workspace must grow during stream capture; call cdc_reserve first";
+        return CDC_ENOMEM;
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) { set_error("hipStreamSynchronize", e); return CDC_EHIP; }
+    if (ws.dev) {
+        (void)hipFree(ws.dev);
+        ws.dev = nullptr;
+        ws.cap = 0;
+    }
+    size_t cap = align_up(std::max(need, (size_t)1 << 20), (size_t)1 << 20);
+    e = hipMalloc(&ws.dev, cap);
+    if (e != hipSuccess) { set_error("hipMalloc workspace", e); return CDC_ENOMEM; }
+    ws.cap = cap;
+    // the error word lives at offset 0 and starts cleared
+    e = hipMemsetAsync(ws.dev, 0, 256, st);
+    if (e != hipSuccess) { set_error("hipMemsetAsync", e); return CDC_EHIP; }
+    return CDC_OK;
+}
+
+bool params_valid(uint32_t algo, uint32_t w, uint32_t M) {
+    return algo <= 3 && w >= 1 && (uint64_t)M >= (uint64_t)w + 1 &&
+           (uint64_t)M <= (1ull << 31);
+}
+
+uint64_t choose_segment(uint64_t n) {
+    if (g_segment_bytes) return g_segment_bytes;
+    uint64_t s = align_up(n / kTargetSegments + 1, 16 << 10);
+    return std::min(std::max(s, kMinSeg), kMaxSeg);
+}
+
+uint32_t maxp_blog(uint32_t w) {
+    uint64_t b = std::min<uint64_t>((uint64_t)w + 1, kTile);
+    uint32_t lg = 0;
+    while ((2ull << lg) <= b) lg++;
+    return lg >= 4 ? lg : 0;
+}
+
+// Slots per segment: cuts of a chain through a segment lie in
+// (a, a + S + M) with spacing >= w+1; MAXP candidates lie in [a, a + S + B)
+// with spacing >= w+1.
+uint32_t slots_per_segment(uint32_t algo, uint64_t S, uint32_t w, uint32_t M) {
+    uint64_t span = algo == kMaxp ? S + kTile : S + M;
+    return (uint32_t)(span / ((uint64_t)w + 1) + 2);
+}
+
+uint64_t maxp_blocks(const uint8_t* data, uint64_t n, uint32_t blog) {
+    if (blog == 0) return 0;
+    uint64_t shift = (uintptr_t)data & 15;
+    uint64_t tiles = (n + shift + kTile - 1) / kTile;
+    return tiles * ((uint64_t)kTile >> blog);
+}
+
+struct Layout {
+    size_t err, meta, spec, fix, bmax, bpos, total;
+};
+
+Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool need_fix) {
+    Layout L;
+    size_t off = 0;
+    L.err = off;   off += 256;
+    L.meta = off;  off = align_up(off + items * sizeof(SegMeta), 256);
+    L.spec = off;  off = align_up(off + slots * 4, 256);
+    L.fix = off;   off = align_up(off + (need_fix ? slots * 4 : 0), 256);
+    L.bpos = off;  off = align_up(off + blocks * 8, 256);
+    L.bmax = off;  off = align_up(off + blocks, 256);
+    L.total = off;
+    return L;
+}
+
+template <class T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+}  // namespace
+}  // namespace cdc
+
+using namespace cdc;
+
+extern "C" {
+
+size_t cdc_max_cuts(const cdc_params* p, size_t n) {
+    if (!p || p->window == 0) return 0;
+    return n == 0 ? 0 : (n - 1) / ((size_t)p->window + 1) + 1;
+}
+
+const char* cdc_status_string(int status) {
+    switch (status) {
+        case CDC_OK: return "ok";
+        case CDC_EINVAL: return "invalid argument";
+        case CDC_ENOMEM: return "workspace too small";
+        case CDC_EHIP: return "HIP error";
+        case CDC_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char* cdc_last_error(void) { return t_last_error.c_str(); }
+
+int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block) {
+    if (segment_bytes != 0 && (segment_bytes < 16 || segment_bytes > kMaxSeg))
+        return CDC_EINVAL;
+    if (waves_per_block > 16) return CDC_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_segment_bytes = segment_bytes;
+    g_waves_per_block = waves_per_block ? (int)waves_per_block : 4;
+    return CDC_OK;
+}
+
+int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
+              size_t n, uint64_t* cut_offsets, uint64_t* n_cuts,
+              hipStream_t stream) {
+    t_last_error.clear();
+    if (!p || !n_cuts || (n > 0 && (!data || !cut_offsets)) ||
+        p->flags != 0 || p->reserved != 0 ||
+        !params_valid((uint32_t)algo, p->window, p->max_chunk)) {
+        t_last_error = "invalid argument";
+        return CDC_EINVAL;
+    }
+    if (n == 0) {
+        hipError_t e = launch_set_u64(n_cuts, 0, stream);
+        if (e != hipSuccess) { set_error("launch", e); return CDC_EHIP; }
+        return CDC_OK;
+    }
+    JobDesc jd{};
+    jd.data = data;
+    jd.n = n;
+    jd.cuts = cut_offsets;
+    jd.n_cuts = n_cuts;
+    jd.status = nullptr;
+    jd.algo = (uint32_t)algo;
+    jd.w = p->window;
+    jd.M = p->max_chunk;
+    int wpb;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        jd.seg = choose_segment(n);
+        wpb = g_waves_per_block;
+    }
+    jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
+    jd.item0 = 0;
+    jd.cap = slots_per_segment(jd.algo, jd.seg, jd.w, jd.M);
+    jd.slot0 = 0;
+    jd.blk0 = 0;
+    jd.blog = jd.algo == kMaxp ? maxp_blog(jd.w) : 0;
+    jd.ok = 1;
+    const uint64_t slots = (uint64_t)jd.nseg * jd.cap;
+    const uint64_t blocks = jd.algo == kMaxp ? maxp_blocks(data, n, jd.blog) : 0;
+    const Layout L = layout(jd.nseg, slots, blocks, jd.algo != kMaxp);
+
+    std::lock_guard<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    int rc = ensure(ws, L.total, stream);
+    if (rc != CDC_OK) return rc;
+    Plan P{};
+    P.jobs = nullptr;
+    P.one = jd;
+    P.one_items = jd.nseg;
+    hipError_t e;
+    if (jd.algo == kMaxp) {
+        e = launch_maxp(P, jd.nseg, 1, nullptr, at<SegMeta>(ws.dev, L.meta),
+                        at<uint32_t>(ws.dev, L.spec), at<uint8_t>(ws.dev, L.bmax),
+                        at<int64_t>(ws.dev, L.bpos), at<uint32_t>(ws.dev, L.err),
+                        wpb, jd.blog != 0, stream);
+    } else {
+        e = launch_ram_ae(P, jd.nseg, 1, nullptr, at<SegMeta>(ws.dev, L.meta),
+                          at<uint32_t>(ws.dev, L.spec), at<uint32_t>(ws.dev, L.fix),
+                          at<uint32_t>(ws.dev, L.err), wpb, stream);
+    }
+    if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
+    return CDC_OK;
+}
+
+int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
+                uint32_t min_window) {
+    t_last_error.clear();
+    if (min_window == 0 || max_jobs == 0) return CDC_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    ws.res_bytes = max_total_bytes;
+    ws.res_jobs = max_jobs;
+    ws.res_min_w = min_window;
+    // single-buffer calls of up to max_total_bytes with windows >= min_window
+    const uint64_t S = choose_segment(max_total_bytes);
+    const uint64_t nseg = (max_total_bytes + S - 1) / S + max_jobs;
+    const uint64_t cap = (S + (1ull << 31)) / ((uint64_t)min_window + 1) + 2;
+    const uint64_t slots = std::min<uint64_t>(nseg * cap,
+                                              max_total_bytes / (min_window + 1) + 4 * nseg);
+    const Layout L = layout(nseg, slots, max_total_bytes / 16 + 64 * nseg, true);
+    return ensure(ws, L.total, stream);
+}
+
+void cdc_release(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    for (auto& kv : g_ws) {
+        if (kv.second.dev) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(kv.first.first);
+            (void)hipFree(kv.second.dev);
+            (void)hipSetDevice(cur);
+        }
+    }
+    g_ws.clear();
+}
+
+int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
+    (void)jobs;
+    (void)n_jobs;
+    (void)stream;
+    t_last_error = "batch path not built yet";
+    return CDC_ENOTSUP;
+}
+
+int cdc_check_device_errors(hipStream_t stream) {
+    std::lock_guard<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    if (!ws.dev) return 0;
+    uint32_t flags = 0;
+    hipError_t e = hipMemcpyAsync(&flags, ws.dev, 4, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ws.dev, 0, 4, stream);
+    if (e != hipSuccess) { set_error("error word", e); return CDC_EHIP; }
+    return (int)flags;
+}
+
+}  // extern "C"

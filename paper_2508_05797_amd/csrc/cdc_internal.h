@@ -1,0 +1,78 @@
+// Internal structures shared by the HIP kernels and the host runtime of
+// libcdc.  Not part of the public ABI (include/cdc.h is).
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace cdc {
+
+constexpr int kWave = 64;          // lanes per wavefront on CDNA
+constexpr int kTile = 1024;        // bytes one wave stages per step (64 x 16 B)
+
+enum Algo : uint32_t { kRam = 0, kAe = 1, kMaxp = 2, kAeMin = 3 };
+
+// One job as the kernels see it: the caller's descriptor plus the plan
+// (segmentation and workspace slots) computed for it.
+struct JobDesc {
+    const uint8_t* data;
+    uint64_t n;
+    uint64_t* cuts;          // caller's output offsets
+    uint64_t* n_cuts;        // caller's output count
+    int32_t* status;         // caller's status word (batch) or nullptr
+    uint32_t algo;
+    uint32_t w;
+    uint32_t M;
+    uint32_t nseg;           // number of segments (work items) of this job
+    uint64_t seg;            // segment length S in bytes
+    uint32_t item0;          // index of the first work item of this job
+    uint32_t cap;            // cut (or candidate) slots per segment
+    uint64_t slot0;          // first slot of this job in the slot arrays
+    uint64_t blk0;           // first block-summary entry (MAXP)
+    uint32_t blog;           // log2 of the MAXP block length (0: direct path)
+    int32_t ok;              // 1 if the job passed validation
+};
+
+// Per-segment record of the speculate / fix-up / resolve passes.
+struct SegMeta {
+    uint64_t exit;           // exit of the chain speculated from the segment start
+    uint64_t h;              // exit of the chain from the resolved entry
+    uint32_t nspec;          // speculative cuts (or MAXP candidates) stored
+    uint32_t nfix;           // fix-up cuts stored
+    uint32_t mi;             // first speculative cut that is also a true cut
+    uint32_t merged;         // 1 if the fix-up chain met the speculative chain
+    uint64_t out;            // offset of this segment's cuts in the output
+};
+
+struct Item {
+    uint32_t job;
+    uint32_t seg;
+};
+
+// Where a kernel finds its work: a device job table with an item table
+// (batch), or one job passed by value.
+struct Plan {
+    const JobDesc* jobs;     // device job table, or nullptr for one job
+    const Item* items;       // device item table (with jobs)
+    const uint32_t* n_items; // device item count (with jobs)
+    JobDesc one;             // the single job (jobs == nullptr)
+    uint32_t one_items;      // its item count
+};
+
+// Flags raised on the device (workspace word) when a bound was violated.
+enum : uint32_t { kErrOverflow = 1u };
+
+// Host-side launch sequences (defined with the kernels).
+hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
+                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
+                         SegMeta* meta, uint32_t* spec, uint32_t* fix,
+                         uint32_t* err, int waves_per_block, hipStream_t st);
+hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
+                       const uint32_t* n_jobs_d, SegMeta* meta,
+                       uint32_t* cand, uint8_t* bmax, int64_t* bpos,
+                       uint32_t* err, int waves_per_block, bool any_blocks,
+                       hipStream_t st);
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st);
+hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
+
+}  // namespace cdc

@@ -1,0 +1,58 @@
+"""The C ABI library loads and exports every function include/cdc.h declares
+(no GPU needed: nothing is called that touches a device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cdc.h")
+LIB = os.path.join(ROOT, "paper_2508_05797_amd", "libcdc.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cdc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ["cdc_chunk", "cdc_chunk_batch", "cdc_max_cuts", "cdc_reserve",
+                 "cdc_release", "cdc_status_string", "cdc_last_error"]:
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcdc.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcdc.so not built")
+def test_host_only_entry_points():
+    from paper_2508_05797_amd import binding
+    L = binding.lib()
+    assert L.cdc_status_string(0) == b"ok"
+    assert L.cdc_status_string(-1) == b"invalid argument"
+    p = binding.Params(4096, 65536, 0, 0)
+    assert L.cdc_max_cuts(ctypes.byref(p), 0) == 0
+    assert L.cdc_max_cuts(ctypes.byref(p), 1) == 1
+    assert L.cdc_max_cuts(ctypes.byref(p), 4097) == 1
+    assert L.cdc_max_cuts(ctypes.byref(p), 4098) == 2
+    assert L.cdc_max_cuts(ctypes.byref(p), 1 << 30) == (((1 << 30) - 1) // 4097) + 1
+    # invalid parameters are rejected before anything touches a device
+    for w, M in [(0, 10), (10, 10), (10, (1 << 31) + 1)]:
+        q = binding.Params(w, M, 0, 0)
+        rc = L.cdc_chunk(0, ctypes.byref(q), ctypes.c_void_p(1), 100,
+                         ctypes.c_void_p(1), ctypes.c_void_p(1), None)
+        assert rc == -1
+    q = binding.Params(16, 100, 0, 0)
+    assert L.cdc_chunk(7, ctypes.byref(q), ctypes.c_void_p(1), 100,
+                       ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+    assert L.cdc_chunk(0, ctypes.byref(q), None, 100, ctypes.c_void_p(1),
+                       ctypes.c_void_p(1), None) == -1
+    assert L.cdc_set_tuning(8, 0) == -1
+    assert L.cdc_set_tuning(0, 0) == 0

@@ -1,0 +1,144 @@
+"""Parity of the HIP path with the oracle, element by element (GPU).
+
+Cut offsets are integers, so the bar is bit-exact equality with the oracle
+on the same seeded bytes.  Inputs: the 8 MiB uniform RAM workload, an
+adversarial suite (constant runs, ramps, sawtooth near the window length,
+two-valued and spike data, Zipf text), ragged lengths around the window,
+the maximum chunk and the 1 KiB tile, every base-pointer misalignment, and
+segment lengths from far below to far above the window (the result may not
+depend on how the stream is split).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_05797_amd import binding, datagen
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ["ram", "ae", "maxp", "ae_min"]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available()
+    binding.lib()
+    yield
+    binding.set_tuning(0, 0)
+    assert binding.device_errors() == 0
+
+
+def gpu_cuts(x, algo, w, M, offset=0):
+    """Chunk x on the device; offset > 0 places it at an unaligned address."""
+    buf = torch.zeros(x.size + offset + 64, dtype=torch.uint8, device="cuda")
+    if x.size:
+        buf[offset:offset + x.size] = torch.from_numpy(x).cuda()
+    view = buf[offset:offset + x.size]
+    return binding.chunk(view, algo, w, M).cpu().numpy().astype(np.uint64)
+
+
+def check(x, algo, w, M, offset=0, tag=""):
+    say("case", tag, algo, "n=%d w=%d M=%d off=%d" % (x.size, w, M, offset))
+    got = gpu_cuts(x, algo, w, M, offset)
+    exp = oracle.chunk(algo, x, w, M)
+    if got.size != exp.size or not np.array_equal(got, exp):
+        k = 0
+        while k < min(got.size, exp.size) and got[k] == exp[k]:
+            k += 1
+        raise AssertionError(
+            "%s %s n=%d w=%d M=%d off=%d: %d vs %d cuts, first diff at %d: "
+            "gpu %s oracle %s" % (tag, algo, x.size, w, M, offset, got.size,
+                                  exp.size, k, got[k:k + 3], exp[k:k + 3]))
+
+
+def test_ram_8mib_uniform():
+    x = datagen.uniform(8 << 20, 1)
+    check(x, "ram", 4096, 65536, tag="C1")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_mixed_16mib(algo):
+    x, _ = datagen.mixed_stream(256, 2)
+    w = 2048 if algo == "maxp" else 4096
+    check(x, algo, w, 65536, tag="mix")
+
+
+def adversarial(n, w, rng):
+    yield "zeros", np.zeros(n, np.uint8)
+    yield "ff", np.full(n, 255, np.uint8)
+    yield "const7f", np.full(n, 0x7F, np.uint8)
+    yield "ramp_up", (np.arange(n) % 256).astype(np.uint8)
+    yield "ramp_down", (255 - np.arange(n) % 256).astype(np.uint8)
+    for p in (w - 1, w, w + 1, w + 2):
+        yield "saw%d" % p, (np.arange(n) % max(p, 1) * 255 // max(p, 1)).astype(np.uint8)
+    yield "two_val", rng.choice(np.array([0x7F, 0x80], np.uint8), n)
+    yield "signed_trap", rng.choice(np.array([0, 0x7F, 0x80, 0xFF], np.uint8), n)
+    sp = np.zeros(n, np.uint8)
+    sp[rng.integers(0, n, max(1, n // (3 * w + 1)))] = 255
+    yield "spikes", sp
+    yield "zipf", datagen.zipf_table(datagen.PRINTABLE)[rng.integers(0, 1 << 20, n)]
+    yield "uniform", rng.integers(0, 256, n).astype(np.uint8)
+    runs = np.repeat(rng.integers(0, 256, n // 700 + 1).astype(np.uint8), 700)[:n]
+    yield "runs", runs
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("w,M", [(1, 2), (3, 7), (15, 16), (64, 1000),
+                                 (600, 4000), (4096, 65536)])
+def test_adversarial(algo, w, M):
+    rng = np.random.default_rng(w * 7 + M)
+    n = max(3 * M + 333, 20000)
+    for name, x in adversarial(n, w, rng):
+        check(x, algo, w, M, tag=name)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_ragged_lengths(algo):
+    rng = np.random.default_rng(4)
+    w, M = 100, 700
+    base = rng.integers(0, 256, 40000).astype(np.uint8)
+    lens = [0, 1, 2, 15, 16, 17, w - 1, w, w + 1, w + 2, 2 * w + 1, M - 1, M,
+            M + 1, 1023, 1024, 1025, 16383, 16385, 39999]
+    for n in lens:
+        check(base[:n], algo, w, M, tag="len")
+        check(np.zeros(n, np.uint8), algo, w, M, tag="len0")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_base_alignment(algo):
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 256, 30011).astype(np.uint8)
+    x[10000:14000] = 3
+    for off in range(16):
+        check(x, algo, 200, 3000, offset=off, tag="align")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_segment_invariance(algo):
+    """The split into segments is a tuning choice; offsets must not move."""
+    x, _ = datagen.mixed_stream(24, 9, block=4096)
+    x = np.concatenate([x, np.full(50000, 9, np.uint8), x[:7777]])
+    w = 300 if algo != "maxp" else 100
+    exp = oracle.chunk(algo, x, w, 5000)
+    try:
+        for seg in [16, 100, 1000, 1024, 4099, 5000, 65536, 1 << 20]:
+            binding.set_tuning(seg, 0)
+            say("case seg", algo, seg)
+            got = gpu_cuts(x, algo, w, 5000)
+            assert np.array_equal(got, exp), (algo, seg)
+    finally:
+        binding.set_tuning(0, 0)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("algo", ["ram", "ae", "maxp"])
+def test_mixed_1gib(algo):
+    """The 1 GiB mixed stream at full size, whole cut list vs the oracle."""
+    x, _ = datagen.mixed_stream(16384, 2024)
+    w = 2048 if algo == "maxp" else 4096
+    check(x, algo, w, 65536, tag="C2")
