@@ -51,8 +51,8 @@ typedef enum {
     CDC_AE_MIN = 3
 } cdc_algo;
 
-/* Chunker parameters.  window (w) >= 1; window + 1 <= max_chunk <= 2^31;
- * flags and reserved must be 0. */
+/* Chunker parameters.  window (w) >= 1; window + 1 <= max_chunk <= 2^28
+ * (268,435,456); flags and reserved must be 0. */
 typedef struct {
     uint32_t window;
     uint32_t max_chunk;
@@ -146,11 +146,31 @@ const char* cdc_status_string(int status);
 const char* cdc_last_error(void);
 
 /*
- * Tuning knobs (bytes per segment of the segment-parallel chain search and
- * waves per workgroup).  0 restores the built-in choice.  They change only
- * speed, never the offsets.  Returns CDC_OK or CDC_EINVAL.
+ * Tuning knobs: bytes per segment of the segment-parallel chain search
+ * (16 .. 2^28), waves per workgroup (1 .. 4), and whether RAM / AE
+ * speculation also runs a front of extra walkers near each segment start
+ * (nonzero: on).  0 restores the built-in choice.  They change only speed,
+ * never the offsets.  Returns CDC_OK or CDC_EINVAL.
  */
-int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block);
+int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block,
+                   uint32_t front_walkers);
+
+/*
+ * Kernel timing (tracing).  level 0: off; 1: HIP events around the main
+ * kernel of each call (the speculation pass of RAM / AE, the block-summary
+ * pass of MAXP); 2: around every kernel.  Events are recorded on the stream
+ * of the call.  Returns CDC_OK or CDC_EINVAL.
+ */
+int cdc_set_profiling(int level);
+
+/*
+ * Synchronise `stream` and report the kernels timed on it since the last
+ * report: for up to max_kernels distinct kernel names, names[i] (static
+ * strings), calls[i] and total_ms[i].  Returns the number of names filled,
+ * or a negative status.  Clears the records.
+ */
+int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
+                     double* total_ms, int max_kernels);
 
 /*
  * Diagnostic: synchronise `stream`, return and clear the sticky flags the

@@ -64,7 +64,13 @@ def lib():
         L.cdc_last_error.restype = ctypes.c_char_p
         L.cdc_last_error.argtypes = []
         L.cdc_set_tuning.restype = _I
-        L.cdc_set_tuning.argtypes = [_U64, _U32]
+        L.cdc_set_tuning.argtypes = [_U64, _U32, _U32]
+        L.cdc_set_profiling.restype = _I
+        L.cdc_set_profiling.argtypes = [_I]
+        L.cdc_kernel_times.restype = _I
+        L.cdc_kernel_times.argtypes = [_V, ctypes.POINTER(ctypes.c_char_p),
+                                       ctypes.POINTER(ctypes.c_uint32),
+                                       ctypes.POINTER(ctypes.c_double), _I]
         L.cdc_check_device_errors.restype = _I
         L.cdc_check_device_errors.argtypes = [_V]
         _lib = L
@@ -114,8 +120,8 @@ def chunk(data, algo, window, max_chunk, stream=None):
     return cuts[:int(n_cuts.item())]
 
 
-def set_tuning(segment_bytes=0, waves_per_block=0):
-    _check(lib().cdc_set_tuning(segment_bytes, waves_per_block))
+def set_tuning(segment_bytes=0, waves_per_block=0, front_walkers=0):
+    _check(lib().cdc_set_tuning(segment_bytes, waves_per_block, front_walkers))
 
 
 def device_errors(stream=None):
@@ -123,6 +129,23 @@ def device_errors(stream=None):
     if rc < 0:
         _check(rc)
     return rc
+
+
+def set_profiling(level):
+    """0 off; 1 events around the main kernel of each call; 2 every kernel."""
+    _check(lib().cdc_set_profiling(level))
+
+
+def kernel_times(stream=None, max_kernels=16):
+    """{kernel name: (calls, total ms)} recorded on the stream since the last
+    report (synchronises the stream)."""
+    names = (ctypes.c_char_p * max_kernels)()
+    calls = (ctypes.c_uint32 * max_kernels)()
+    tot = (ctypes.c_double * max_kernels)()
+    k = lib().cdc_kernel_times(_stream(stream), names, calls, tot, max_kernels)
+    if k < 0:
+        _check(k)
+    return {names[i].decode(): (int(calls[i]), float(tot[i])) for i in range(k)}
 
 
 def release():

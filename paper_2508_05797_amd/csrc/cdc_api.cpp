@@ -32,14 +32,62 @@ void set_error(const char* what, hipError_t e) {
 // Tuning (speed only; never changes the offsets).
 uint64_t g_segment_bytes = 0;
 int g_waves_per_block = 4;
+uint32_t g_front = 0;
 
 constexpr uint64_t kMinSeg = 64 << 10;
-constexpr uint64_t kMaxSeg = 1ull << 30;
-constexpr uint64_t kTargetSegments = 4096;
+// Segments and chunks are at most 2^28 bytes: the chain kernels keep
+// positions as 32-bit offsets from the segment start.
+constexpr uint64_t kMaxSeg = 1ull << 28;
+constexpr uint64_t kMaxChunkLimit = 1ull << 28;
+// RAM / AE: few long segments, so that speculated chains rejoin the true
+// chain inside their segment; MAXP has no chain to rejoin (its candidates do
+// not depend on the chunk start) and splits finely for load balance.
+constexpr uint64_t kChainSegment = 1 << 20;
+constexpr uint64_t kMaxpSegment = 64 << 10;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Event pairs around kernels, resolved when the caller asks for them.
+struct EventMarks : Marks {
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    int level = 0;
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    bool open = false;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void begin(const char* name, int lvl, hipStream_t st) override {
+        open = false;
+        if (lvl > level) return;
+        hipEvent_t a = get(), b = get();
+        if (!a || !b) return;
+        (void)hipEventRecord(a, st);
+        recs.push_back({name, a, b});
+        open = true;
+    }
+    void end(int lvl, hipStream_t st) override {
+        if (lvl > level || !open) return;
+        (void)hipEventRecord(recs.back().b, st);
+        open = false;
+    }
+};
+
+int g_profile_level = 0;
+
 struct Workspace {
+    EventMarks marks;
     void* dev = nullptr;
     size_t cap = 0;
     // reservation for batches (bytes, jobs, minimum window)
@@ -90,13 +138,13 @@ int ensure(Workspace& ws, size_t need, hipStream_t st) {
 
 bool params_valid(uint32_t algo, uint32_t w, uint32_t M) {
     return algo <= 3 && w >= 1 && (uint64_t)M >= (uint64_t)w + 1 &&
-           (uint64_t)M <= (1ull << 31);
+           (uint64_t)M <= kMaxChunkLimit;
 }
 
-uint64_t choose_segment(uint64_t n) {
+uint64_t choose_segment(uint32_t algo, uint64_t n) {
     if (g_segment_bytes) return g_segment_bytes;
-    uint64_t s = align_up(n / kTargetSegments + 1, 16 << 10);
-    return std::min(std::max(s, kMinSeg), kMaxSeg);
+    (void)n;
+    return algo == kMaxp ? kMaxpSegment : kChainSegment;
 }
 
 uint32_t maxp_blog(uint32_t w) {
@@ -121,26 +169,40 @@ uint64_t maxp_blocks(const uint8_t* data, uint64_t n, uint32_t blog) {
     return tiles * ((uint64_t)kTile >> blog);
 }
 
+template <class T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
 struct Layout {
-    size_t err, meta, spec, fix, bmax, bpos, total;
+    size_t err, meta, spec, fix, front, fmeta, bmax, bpos, total;
 };
 
-Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool need_fix) {
+Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain) {
     Layout L;
     size_t off = 0;
+    const uint64_t fl = chain ? items * kFront : 0;
     L.err = off;   off += 256;
     L.meta = off;  off = align_up(off + items * sizeof(SegMeta), 256);
     L.spec = off;  off = align_up(off + slots * 4, 256);
-    L.fix = off;   off = align_up(off + (need_fix ? slots * 4 : 0), 256);
+    L.fix = off;   off = align_up(off + (chain ? slots * 4 : 0), 256);
+    L.front = off; off = align_up(off + fl * (kFrontCap + 1) * 4, 256);
+    L.fmeta = off; off = align_up(off + fl * sizeof(FrontMeta), 256);
     L.bpos = off;  off = align_up(off + blocks * 8, 256);
     L.bmax = off;  off = align_up(off + blocks, 256);
     L.total = off;
     return L;
 }
 
-template <class T>
-T* at(void* base, size_t off) {
-    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+ChainWs chain_ws(void* base, const Layout& L) {
+    ChainWs w;
+    w.meta = at<SegMeta>(base, L.meta);
+    w.spec = at<uint32_t>(base, L.spec);
+    w.fix = at<uint32_t>(base, L.fix);
+    w.front = at<uint32_t>(base, L.front);
+    w.fmeta = at<FrontMeta>(base, L.fmeta);
+    w.err = at<uint32_t>(base, L.err);
+    return w;
 }
 
 }  // namespace
@@ -168,13 +230,15 @@ const char* cdc_status_string(int status) {
 
 const char* cdc_last_error(void) { return t_last_error.c_str(); }
 
-int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block) {
+int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block,
+                   uint32_t front_walkers) {
     if (segment_bytes != 0 && (segment_bytes < 16 || segment_bytes > kMaxSeg))
         return CDC_EINVAL;
-    if (waves_per_block > 16) return CDC_EINVAL;
+    if (waves_per_block > 4) return CDC_EINVAL;   // kernels are built for <= 256 threads
     std::lock_guard<std::mutex> g(g_mu);
     g_segment_bytes = segment_bytes;
     g_waves_per_block = waves_per_block ? (int)waves_per_block : 4;
+    g_front = front_walkers ? 1u : 0u;
     return CDC_OK;
 }
 
@@ -205,8 +269,9 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
     int wpb;
     {
         std::lock_guard<std::mutex> g(g_mu);
-        jd.seg = choose_segment(n);
+        jd.seg = choose_segment(jd.algo, n);
         wpb = g_waves_per_block;
+        jd.front = g_front;
     }
     jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
     jd.item0 = 0;
@@ -227,16 +292,17 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
     P.jobs = nullptr;
     P.one = jd;
     P.one_items = jd.nseg;
+    ws.marks.level = g_profile_level;
+    Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
     hipError_t e;
     if (jd.algo == kMaxp) {
         e = launch_maxp(P, jd.nseg, 1, nullptr, at<SegMeta>(ws.dev, L.meta),
                         at<uint32_t>(ws.dev, L.spec), at<uint8_t>(ws.dev, L.bmax),
                         at<int64_t>(ws.dev, L.bpos), at<uint32_t>(ws.dev, L.err),
-                        wpb, jd.blog != 0, stream);
+                        wpb, jd.blog != 0, stream, mk);
     } else {
-        e = launch_ram_ae(P, jd.nseg, 1, nullptr, at<SegMeta>(ws.dev, L.meta),
-                          at<uint32_t>(ws.dev, L.spec), at<uint32_t>(ws.dev, L.fix),
-                          at<uint32_t>(ws.dev, L.err), wpb, stream);
+        e = launch_ram_ae(P, jd.nseg, 1, nullptr, chain_ws(ws.dev, L), wpb,
+                          stream, mk);
     }
     if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
     return CDC_OK;
@@ -252,9 +318,9 @@ int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
     ws.res_jobs = max_jobs;
     ws.res_min_w = min_window;
     // single-buffer calls of up to max_total_bytes with windows >= min_window
-    const uint64_t S = choose_segment(max_total_bytes);
+    const uint64_t S = kMinSeg;
     const uint64_t nseg = (max_total_bytes + S - 1) / S + max_jobs;
-    const uint64_t cap = (S + (1ull << 31)) / ((uint64_t)min_window + 1) + 2;
+    const uint64_t cap = (S + kMaxChunkLimit) / ((uint64_t)min_window + 1) + 2;
     const uint64_t slots = std::min<uint64_t>(nseg * cap,
                                               max_total_bytes / (min_window + 1) + 4 * nseg);
     const Layout L = layout(nseg, slots, max_total_bytes / 16 + 64 * nseg, true);
@@ -281,6 +347,43 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
     (void)stream;
     t_last_error = "batch path not built yet";
     return CDC_ENOTSUP;
+}
+
+int cdc_set_profiling(int level) {
+    if (level < 0 || level > 2) return CDC_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_profile_level = level;
+    return CDC_OK;
+}
+
+int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
+                     double* total_ms, int max_kernels) {
+    std::lock_guard<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { set_error("hipStreamSynchronize", e); return CDC_EHIP; }
+    int used = 0;
+    for (auto& r : ws.marks.recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.f;
+        int i = 0;
+        while (i < used && strcmp(names[i], r.name) != 0) i++;
+        if (i == used) {
+            if (used == max_kernels) continue;
+            names[used] = r.name;
+            calls[used] = 0;
+            total_ms[used] = 0.0;
+            used++;
+        }
+        calls[i]++;
+        total_ms[i] += ms;
+    }
+    for (auto& r : ws.marks.recs) {
+        ws.marks.pool.push_back(r.a);
+        ws.marks.pool.push_back(r.b);
+    }
+    ws.marks.recs.clear();
+    return used;
 }
 
 int cdc_check_device_errors(hipStream_t stream) {

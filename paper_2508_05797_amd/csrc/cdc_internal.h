@@ -30,18 +30,47 @@ struct JobDesc {
     uint64_t slot0;          // first slot of this job in the slot arrays
     uint64_t blk0;           // first block-summary entry (MAXP)
     uint32_t blog;           // log2 of the MAXP block length (0: direct path)
+    uint32_t front;          // 1: speculate with a front of extra walkers
     int32_t ok;              // 1 if the job passed validation
+};
+
+// Speculation front: besides the main walker started at the segment start,
+// kFront walkers start at evenly spaced offsets within the first chunk's
+// length, so that a chain entering the segment anywhere there has recorded
+// walkers close on both sides and meets one of them within a few chunks.
+constexpr int kFront = 7;
+constexpr int kFrontCap = 48;             // positions kept per front walker
+constexpr int kMaxPieces = kFront + 1;    // walkers a resolved chain can visit
+
+// How a front walker ended: coalesced into another walker (its id), left
+// the segment (kEndExit), or was cut off after kFrontCap positions.
+enum : uint32_t { kEndExit = 0xFE, kEndTrunc = 0xFF, kEndAlive = 0xFD };
+
+struct FrontMeta {
+    uint32_t count;          // positions stored (the first is the start)
+    uint32_t end;            // walker id it merged into, or kEnd*
+    uint32_t dpos;           // where it ended, relative to the segment start
+    uint32_t pad;
+};
+
+// A run of stored positions [lo, hi) of one walker's list (0: main walker,
+// 1..kFront: front walkers) that belongs to the resolved chain.
+struct Piece {
+    uint32_t list, lo, hi, pad;
 };
 
 // Per-segment record of the speculate / fix-up / resolve passes.
 struct SegMeta {
-    uint64_t exit;           // exit of the chain speculated from the segment start
-    uint64_t h;              // exit of the chain from the resolved entry
-    uint32_t nspec;          // speculative cuts (or MAXP candidates) stored
-    uint32_t nfix;           // fix-up cuts stored
-    uint32_t mi;             // first speculative cut that is also a true cut
-    uint32_t merged;         // 1 if the fix-up chain met the speculative chain
+    uint64_t exit;           // exit of the main walker (speculative exit)
+    uint64_t h;              // where the chain from the resolved entry leaves
     uint64_t out;            // offset of this segment's cuts in the output
+    uint32_t nspec;          // main-walker cuts stored
+    uint32_t nfix;           // fix-up cuts stored
+    uint32_t count;          // cuts this segment contributes
+    uint32_t merged;         // 1 if the chain met a recorded walker
+    uint32_t npieces;
+    uint32_t nfront;         // front walkers started
+    Piece pieces[kMaxPieces];
 };
 
 struct Item {
@@ -62,16 +91,32 @@ struct Plan {
 // Flags raised on the device (workspace word) when a bound was violated.
 enum : uint32_t { kErrOverflow = 1u };
 
+// Host-side event marks around kernels (tracing); nullptr when off.
+struct Marks {
+    virtual void begin(const char* name, int level, hipStream_t st) = 0;
+    virtual void end(int level, hipStream_t st) = 0;
+};
+
 // Host-side launch sequences (defined with the kernels).
+// Workspace of the RAM / AE passes.
+struct ChainWs {
+    SegMeta* meta;           // per item
+    uint32_t* spec;          // main-walker cuts, cap per item (job slots)
+    uint32_t* fix;           // fix-up cuts, cap per item (job slots)
+    uint32_t* front;         // kFront lists of kFrontCap+1 per item
+    FrontMeta* fmeta;        // kFront per item
+    uint32_t* err;
+};
+
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
-                         SegMeta* meta, uint32_t* spec, uint32_t* fix,
-                         uint32_t* err, int waves_per_block, hipStream_t st);
+                         const ChainWs& ws, int waves_per_block,
+                         hipStream_t st, Marks* marks);
 hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                        const uint32_t* n_jobs_d, SegMeta* meta,
                        uint32_t* cand, uint8_t* bmax, int64_t* bpos,
                        uint32_t* err, int waves_per_block, bool any_blocks,
-                       hipStream_t st);
+                       hipStream_t st, Marks* marks);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st);
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 

@@ -1,0 +1,332 @@
+// MAXP boundary finding on gfx950, and small utility kernels.
+//
+// MAXP (Section 2.1 "MAXP", Fig. 2b; Section 4.3) cuts right after a byte
+// that is strictly greater than the w bytes before and the w bytes after
+// it.  That test does not depend on where the current chunk starts, so the
+// candidates are found fully in parallel: a strict local maximum over +-w is
+// the unique maximum of every block of at most w+1 bytes that contains it
+// (the extreme byte search of Section 4.1 over blocks), and each block's
+// unique maximum is then checked against the +-w window.  Given the sorted
+// candidates, the chain is arithmetic: from a chunk start s a candidate q
+// ends the chunk iff (q - s) mod M >= w (the forced cuts at s+M, s+2M, ...
+// leave it at least w bytes into its chunk).
+#include "wave.h"
+
+namespace cdc {
+
+// ------------------------------------------------------------ MAXP
+
+// Block summaries.  Blocks are 2^blog bytes aligned in the address space
+// (block beta covers positions [beta*B - shift, (beta+1)*B - shift)); bytes
+// outside the job count as 0.  For each block: its maximum, and the position
+// of that maximum if it occurs exactly once (else -1).  A strict local
+// maximum over +-w is the unique maximum of its block whenever B <= w+1.
+template <int G>
+__device__ void block_summaries(const uint4& v, int64_t tp, int64_t n,
+                                uint8_t* bmax, int64_t* bpos, int64_t beta0) {
+    const int64_t lp = tp + 16 * (int64_t)lane_id();
+    uint4 x = v;
+    if (lp < 0 || lp + 16 > n) {
+        const int a = (int)min(max(-lp, (int64_t)0), (int64_t)16);
+        const int b = (int)min(max(n - lp, (int64_t)0), (int64_t)16);
+        x = keep_bytes(v, a, b);
+    }
+    const uint32_t lm = lane_max16(x);
+    const uint32_t gm_partial = seg_max<G>(lm);
+    const uint32_t last = lane_id() | (G - 1);
+    const uint32_t gm = (uint32_t)__shfl((int)gm_partial, (int)last);
+    const uint32_t eq = (lm == gm) ? 1u : 0u;
+    const uint32_t cnt_partial = seg_sum<G>(eq);
+    const uint32_t cnt = (uint32_t)__shfl((int)cnt_partial, (int)last);
+    const int64_t beta = beta0 + (int64_t)(lane_id() / G);
+    if (cnt != 1) {
+        if (lane_id() == last) {
+            bmax[beta] = (uint8_t)gm;
+            bpos[beta] = -1;
+        }
+    } else if (eq) {
+        // the only lane holding the maximum: is it unique among its bytes?
+        const uint32_t r = gm * 0x01010101u;
+        uint32_t nz = 0, first = 16;
+        const uint32_t d[4] = {x.x ^ r, x.y ^ r, x.z ^ r, x.w ^ r};
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            // high bit of each byte set iff that byte is zero
+            uint32_t t = (d[i] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+            t = ~(t | d[i] | 0x7F7F7F7Fu);
+            nz += __builtin_popcount(t);
+            if (t && first == 16) first = 4 * i + (__builtin_ctz(t) >> 3);
+        }
+        bmax[beta] = (uint8_t)gm;
+        bpos[beta] = (nz == 1 && gm > 0) ? lp + first : -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_maxp_blocks(Plan P, uint8_t* bmax, int64_t* bpos,
+                              uint32_t* err) {
+    JobView J;
+    uint32_t seg;
+    const uint32_t wid = wave_global_id();
+    if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp || J.blog == 0)
+        return;
+    Source src;
+    src.init(J.data, (uint64_t)J.n);
+    // Tiles owned by this segment: those whose first position lies in
+    // [a, b) (tile 0 also owns the bytes before position 0).
+    const int64_t a = (int64_t)seg * J.seg;
+    const int64_t b = min(J.n, a + J.seg);
+    int64_t t0 = (a + src.shift + kTile - 1) >> 10;
+    if (seg == 0) t0 = 0;
+    const int64_t t1 = (b >= J.n) ? ((J.n + src.shift + kTile - 1) >> 10)
+                                  : ((b + src.shift + kTile - 1) >> 10);
+    const int blog = (int)J.blog;
+    const int64_t per_tile = (int64_t)kTile >> blog;   // blocks per tile
+    uint8_t* bm = bmax + J.blk0;
+    int64_t* bp = bpos + J.blk0;
+    for (int64_t t = t0; t < t1; t++) {
+        const uint4 v = src.load<false>(t);
+        const int64_t tp = src.tile_pos(t);
+        const int64_t beta0 = t * per_tile;
+        switch (blog) {
+            case 4: block_summaries<1>(v, tp, J.n, bm, bp, beta0); break;
+            case 5: block_summaries<2>(v, tp, J.n, bm, bp, beta0); break;
+            case 6: block_summaries<4>(v, tp, J.n, bm, bp, beta0); break;
+            case 7: block_summaries<8>(v, tp, J.n, bm, bp, beta0); break;
+            case 8: block_summaries<16>(v, tp, J.n, bm, bp, beta0); break;
+            case 9: block_summaries<32>(v, tp, J.n, bm, bp, beta0); break;
+            default: block_summaries<64>(v, tp, J.n, bm, bp, beta0); break;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t byte_at(const uint8_t* d, int64_t p) {
+    return d[p];
+}
+
+// Exact check that every byte in [lo, hi] is below v.
+__device__ bool all_below(const uint8_t* d, int64_t lo, int64_t hi, uint32_t v) {
+    for (int64_t p = lo; p <= hi; p++)
+        if (byte_at(d, p) >= v) return false;
+    return true;
+}
+
+// Strict local maximum test of position i (w <= i <= n-1-w) from the block
+// summaries: whole blocks inside the window by their maxima, the two partial
+// end blocks by their maxima or, when that is not enough, byte by byte.
+__device__ bool maxp_verify(const JobView& J, const uint8_t* bm, int64_t shift,
+                            int64_t i, uint32_t v) {
+    const int blog = (int)J.blog;
+    const int64_t lo = i - J.w, hi = i + J.w;
+    const int64_t bi = (i + shift) >> blog;
+    const int64_t bl = (lo + shift) >> blog, br = (hi + shift) >> blog;
+    for (int64_t beta = bl + 1; beta < bi; beta++)
+        if (bm[beta] >= v) return false;
+    for (int64_t beta = bi + 1; beta < br; beta++)
+        if (bm[beta] >= v) return false;
+    if (bl < bi && bm[bl] >= v) {
+        const int64_t end = ((bl + 1) << blog) - shift - 1;
+        if (!all_below(J.data, lo, end, v)) return false;
+    }
+    if (br > bi && bm[br] >= v) {
+        const int64_t start = (br << blog) - shift;
+        if (!all_below(J.data, start, hi, v)) return false;
+    }
+    return true;
+}
+
+// Candidates of one segment, in increasing order, relative to the segment
+// start a (positions in [a, b) for the direct path; for the block path, the
+// unique maxima of the blocks whose summaries this segment wrote).
+__global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax, const int64_t* bpos,
+                              SegMeta* meta, uint32_t* cand, uint32_t* err) {
+    JobView J;
+    uint32_t seg;
+    const uint32_t wid = wave_global_id();
+    if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp) return;
+    const int64_t a = (int64_t)seg * J.seg;
+    const int64_t b = min(J.n, a + J.seg);
+    uint32_t* out = cand + J.slot0 + (uint64_t)seg * J.cap;
+    uint32_t cnt = 0;
+    const int64_t lo_ok = J.w, hi_ok = J.n - 1 - J.w;   // full windows
+    if (J.blog == 0) {
+        // Direct test of every position (small windows).
+        for (int64_t base = a; base < b; base += kWave) {
+            const int64_t i = base + lane_id();
+            bool c = false;
+            if (i < b && i >= lo_ok && i <= hi_ok) {
+                const uint32_t v = byte_at(J.data, i);
+                c = all_below(J.data, i - J.w, i - 1, v) &&
+                    all_below(J.data, i + 1, i + J.w, v);
+            }
+            const uint64_t ball = __ballot(c);
+            const uint32_t rank = __builtin_popcountll(ball & ((1ull << lane_id()) - 1));
+            if (c) {
+                if (cnt + rank < J.cap)
+                    out[cnt + rank] = (uint32_t)(i - a);
+                else
+                    atomicOr(err, kErrOverflow);
+            }
+            cnt += (uint32_t)__builtin_popcountll(ball);
+        }
+    } else {
+        Source src;
+        src.init(J.data, (uint64_t)J.n);
+        const int blog = (int)J.blog;
+        const int64_t per_tile = (int64_t)kTile >> blog;
+        int64_t t0 = (a + src.shift + kTile - 1) >> 10;
+        if (seg == 0) t0 = 0;
+        const int64_t t1 = (b >= J.n) ? ((J.n + src.shift + kTile - 1) >> 10)
+                                      : ((b + src.shift + kTile - 1) >> 10);
+        const uint8_t* bm = bmax + J.blk0;
+        const int64_t* bp = bpos + J.blk0;
+        for (int64_t beta = t0 * per_tile; beta < t1 * per_tile; beta += kWave) {
+            const int64_t bb = beta + lane_id();
+            bool c = false;
+            int64_t i = -1;
+            if (bb < t1 * per_tile) {
+                i = bp[bb];
+                if (i >= lo_ok && i <= hi_ok)
+                    c = maxp_verify(J, bm, src.shift, i, bm[bb]);
+            }
+            const uint64_t ball = __ballot(c);
+            const uint32_t rank = __builtin_popcountll(ball & ((1ull << lane_id()) - 1));
+            if (c) {
+                if (cnt + rank < J.cap)
+                    out[cnt + rank] = (uint32_t)(i - a);
+                else
+                    atomicOr(err, kErrOverflow);
+            }
+            cnt += (uint32_t)__builtin_popcountll(ball);
+        }
+    }
+    if (lane_id() == 0) meta[wid].nspec = min(cnt, J.cap);
+}
+
+// The MAXP chain over the candidates (one wave per job).  From a chunk start
+// s a candidate q is a boundary iff (q - s) mod M >= w: the forced cuts
+// s+M, s+2M, ... in between leave it at least w bytes into its chunk.  After
+// a boundary the next candidate is accepted directly unless it lies more
+// than M bytes further on, so runs of accepted candidates are taken 64 at a
+// time.
+__device__ __forceinline__ void put_forced(uint64_t* out, uint64_t& cnt,
+                                           uint64_t room, int64_t s, int64_t t,
+                                           int64_t M) {
+    for (int64_t i = lane_id(); i < t; i += kWave)
+        if (cnt + i < room) out[cnt + i] = (uint64_t)(s + (i + 1) * M);
+    cnt += (uint64_t)t;
+}
+
+__global__ __launch_bounds__(256) void k_maxp_chain(Plan P, uint32_t n_jobs_h, const uint32_t* n_jobs_d,
+                             const SegMeta* meta, const uint32_t* cand,
+                             uint32_t* err) {
+    const uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
+    if (uni(job) >= n_jobs) return;
+    JobView J = view(P.jobs ? P.jobs[uni(job)] : P.one);
+    if (!J.ok || J.algo != kMaxp) return;
+    const int64_t n = J.n, w = J.w, M = J.M;
+    uint64_t* out = J.cuts;
+    const uint64_t room = max_cuts_of(J);
+    uint64_t cnt = 0;
+    int64_t s = 0;
+    for (uint32_t sb = 0; sb < J.nseg; sb += kWave) {
+        const uint32_t my = sb + lane_id();
+        const uint32_t my_nc = my < J.nseg ? meta[J.item0 + my].nspec : 0u;
+        uint64_t has = __ballot(my_nc != 0);
+        while (has) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(has);
+            has &= has - 1;
+            const uint32_t seg = sb + l;
+            const uint32_t nc = __builtin_amdgcn_readlane(my_nc, l);
+            const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
+            const int64_t a = (int64_t)seg * J.seg;
+            for (uint32_t base = 0; base < nc; base += kWave) {
+                const uint32_t k = base + lane_id();
+                const bool valid = k < nc;
+                const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
+                int64_t qprev = __shfl_up(q, 1);
+                uint32_t done = 0;  // lanes below `done` are settled
+                for (;;) {
+                    const bool acc = valid && lane_id() >= done && q >= s &&
+                                     ((q - s) % M) >= w;
+                    const uint64_t ball = __ballot(acc);
+                    if (ball == 0) break;
+                    const uint32_t f = (uint32_t)__builtin_ctzll(ball);
+                    const int64_t qf = uni64(__shfl(q, (int)f));
+                    // accepted run: f, then every next candidate within M+1
+                    const bool brk = lane_id() > f &&
+                                     (!valid || (q - qprev - 1) >= M);
+                    const uint64_t bb = __ballot(brk);
+                    const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
+                    put_forced(out, cnt, room, s, (qf - s) / M, M);
+                    if (lane_id() >= f && lane_id() < g &&
+                        cnt + (lane_id() - f) < room)
+                        out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
+                    cnt += g - f;
+                    s = uni64(__shfl(q, (int)(g - 1))) + 1;
+                    done = g;
+                    if (g >= 64) break;
+                }
+            }
+        }
+    }
+    if (n > 0) {
+        put_forced(out, cnt, room, s, (n - s - 1) / M, M);
+        if (lane_id() == 0 && cnt < room) out[cnt] = (uint64_t)n;
+        cnt++;
+    }
+    if (cnt > room) {   // cannot happen for a correct chain
+        if (lane_id() == 0) atomicOr(err, kErrOverflow);
+        cnt = room;
+    }
+    if (lane_id() == 0) *J.n_cuts = cnt;
+}
+
+// ------------------------------------------------------------ launches
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void k_clear_u32(uint32_t* p, size_t count) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, st, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st) {
+    const uint32_t grid = (uint32_t)min((count + 255) / 256, (size_t)1024);
+    hipLaunchKernelGGL(k_clear_u32, dim3(grid > 0 ? grid : 1), dim3(256), 0,
+                       st, p, count);
+    return hipGetLastError();
+}
+
+#define CDC_LAUNCH(MK, LVL, NAME, ...)                 \
+    do {                                               \
+        if (MK) (MK)->begin(NAME, LVL, st);            \
+        hipLaunchKernelGGL(__VA_ARGS__);               \
+        if (MK) (MK)->end(LVL, st);                    \
+    } while (0)
+
+hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
+                       const uint32_t* n_jobs_d, SegMeta* meta, uint32_t* cand,
+                       uint8_t* bmax, int64_t* bpos, uint32_t* err, int wpb,
+                       bool any_blocks, hipStream_t st, Marks* mk) {
+    const dim3 blk(kWave * wpb), grid((items_upper + wpb - 1) / wpb);
+    if (any_blocks)
+        CDC_LAUNCH(mk, 1, "maxp_blocks", k_maxp_blocks, grid, blk, 0, st, P,
+                   bmax, bpos, err);
+    CDC_LAUNCH(mk, any_blocks ? 2 : 1, "maxp_verify", k_maxp_verify, grid, blk,
+               0, st, P, bmax, bpos, meta, cand, err);
+    const uint32_t jgrid = (jobs_upper + 3) / 4;
+    CDC_LAUNCH(mk, 2, "maxp_chain", k_maxp_chain, dim3(jgrid), dim3(256), 0, st,
+               P, jobs_upper, n_jobs_d, meta, cand, err);
+    return hipGetLastError();
+}
+
+}  // namespace cdc

@@ -44,7 +44,7 @@ def test_host_only_entry_points():
     assert L.cdc_max_cuts(ctypes.byref(p), 4098) == 2
     assert L.cdc_max_cuts(ctypes.byref(p), 1 << 30) == (((1 << 30) - 1) // 4097) + 1
     # invalid parameters are rejected before anything touches a device
-    for w, M in [(0, 10), (10, 10), (10, (1 << 31) + 1)]:
+    for w, M in [(0, 10), (10, 10), (10, (1 << 28) + 1)]:
         q = binding.Params(w, M, 0, 0)
         rc = L.cdc_chunk(0, ctypes.byref(q), ctypes.c_void_p(1), 100,
                          ctypes.c_void_p(1), ctypes.c_void_p(1), None)
@@ -54,5 +54,6 @@ def test_host_only_entry_points():
                        ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
     assert L.cdc_chunk(0, ctypes.byref(q), None, 100, ctypes.c_void_p(1),
                        ctypes.c_void_p(1), None) == -1
-    assert L.cdc_set_tuning(8, 0) == -1
-    assert L.cdc_set_tuning(0, 0) == 0
+    assert L.cdc_set_tuning(8, 0, 0) == -1
+    assert L.cdc_set_tuning(0, 9, 0) == -1
+    assert L.cdc_set_tuning(0, 0, 0) == 0

@@ -135,6 +135,22 @@ def test_segment_invariance(algo):
         binding.set_tuning(0, 0)
 
 
+@pytest.mark.parametrize("algo", ["ram", "ae", "ae_min"])
+@pytest.mark.parametrize("seg", [4096, 65536, 300000, 1 << 20])
+def test_front_walkers(algo, seg):
+    """Speculation with the extra front walkers (windows of at least one
+    tile) must give the same offsets."""
+    x, _ = datagen.mixed_stream(48, 12)
+    exp = oracle.chunk(algo, x, 1500, 9000)
+    try:
+        binding.set_tuning(seg, 0, 1)
+        say("case front", algo, seg)
+        got = gpu_cuts(x, algo, 1500, 9000)
+        assert np.array_equal(got, exp), (algo, seg)
+    finally:
+        binding.set_tuning(0, 0, 0)
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("algo", ["ram", "ae", "maxp"])
 def test_mixed_1gib(algo):
