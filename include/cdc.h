@@ -129,12 +129,21 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream);
 
 /*
  * Pre-size the workspace of `stream` for batches of at most max_jobs jobs
- * holding at most max_total_bytes bytes in total, with windows >= min_window.
- * Also covers single-buffer calls of up to max_total_bytes bytes.  Call it
- * outside stream capture.  Returns CDC_OK, CDC_EINVAL or CDC_EHIP.
+ * holding at most max_total_bytes bytes in total, with windows >= min_window
+ * and max_chunk <= max_chunk.  Also covers single-buffer calls of up to
+ * max_total_bytes bytes with such parameters.  Call it outside stream
+ * capture.  Returns CDC_OK, CDC_EINVAL, CDC_ENOMEM or CDC_EHIP.
  */
 int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
-                uint32_t min_window);
+                uint32_t min_window, uint32_t max_chunk);
+
+/*
+ * The plain alternative to cdc_chunk_batch: one cdc_chunk call per job, in
+ * order, on `stream`.  host_jobs is a HOST array; each job's status field
+ * receives the return code of its call.  Returns CDC_OK, the first error of
+ * a job, or CDC_EHIP (then the remaining jobs are not enqueued).
+ */
+int cdc_chunk_each(cdc_job* host_jobs, uint32_t n_jobs, hipStream_t stream);
 
 /* Free every workspace owned by the library (after all work completed). */
 void cdc_release(void);

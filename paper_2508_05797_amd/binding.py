@@ -7,6 +7,7 @@ It raises if the library has not been built (there is no CPU fallback).
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,7 +57,9 @@ def lib():
         L.cdc_chunk_batch.restype = _I
         L.cdc_chunk_batch.argtypes = [_V, _U32, _V]
         L.cdc_reserve.restype = _I
-        L.cdc_reserve.argtypes = [_V, _SZ, _U32, _U32]
+        L.cdc_reserve.argtypes = [_V, _SZ, _U32, _U32, _U32]
+        L.cdc_chunk_each.restype = _I
+        L.cdc_chunk_each.argtypes = [_V, _U32, _V]
         L.cdc_release.restype = None
         L.cdc_release.argtypes = []
         L.cdc_status_string.restype = ctypes.c_char_p
@@ -146,6 +149,80 @@ def kernel_times(stream=None, max_kernels=16):
     if k < 0:
         _check(k)
     return {names[i].decode(): (int(calls[i]), float(tot[i])) for i in range(k)}
+
+
+def reserve(max_total_bytes, max_jobs, min_window, max_chunk, stream=None):
+    """Pre-size the stream's workspace (needed before capturing batches)."""
+    _check(lib().cdc_reserve(_stream(stream), max_total_bytes, max_jobs,
+                             min_window, max_chunk))
+
+
+JOB_DTYPE = np.dtype([("data", "<u8"), ("n", "<u8"), ("cut_offsets", "<u8"),
+                      ("n_cuts", "<u8"), ("algo", "<u4"), ("window", "<u4"),
+                      ("max_chunk", "<u4"), ("status", "<i4")])
+assert JOB_DTYPE.itemsize == ctypes.sizeof(Job) == 48
+
+
+class Batch:
+    """Many buffers inside one uint8 device tensor, with one output area.
+
+    ``offsets``/``lengths`` (host integer arrays) locate each buffer in
+    ``data``; ``algo``, ``window`` and ``max_chunk`` are scalars or per-job
+    arrays.  The job descriptors live in device memory (``jobs``) and, for the
+    plain path, in host memory (``host_jobs``)."""
+
+    def __init__(self, data, offsets, lengths, algo, window, max_chunk):
+        assert data.dtype == torch.uint8 and data.is_cuda
+        n_jobs = len(lengths)
+        lengths = np.asarray(lengths, dtype=np.uint64)
+        offsets = np.asarray(offsets, dtype=np.uint64)
+        algos = np.broadcast_to(np.asarray(
+            [algo_id(a) for a in np.atleast_1d(algo)], np.uint32), (n_jobs,))
+        windows = np.broadcast_to(np.asarray(window, np.uint32), (n_jobs,))
+        maxc = np.broadcast_to(np.asarray(max_chunk, np.uint32), (n_jobs,))
+        room = np.where(lengths > 0,
+                        (lengths - 1) // (windows.astype(np.uint64) + 1) + 1, 0)
+        room = np.maximum(room, 1).astype(np.uint64)
+        self.cut_base = np.zeros(n_jobs + 1, np.uint64)
+        np.cumsum(room, out=self.cut_base[1:])
+        dev = data.device
+        self.data = data
+        self.cuts = torch.empty(int(self.cut_base[-1]), dtype=torch.int64,
+                                device=dev)
+        self.n_cuts = torch.zeros(n_jobs, dtype=torch.int64, device=dev)
+        t = np.zeros(n_jobs, JOB_DTYPE)
+        t["data"] = data.data_ptr() + offsets
+        t["n"] = lengths
+        t["cut_offsets"] = self.cuts.data_ptr() + 8 * self.cut_base[:-1]
+        t["n_cuts"] = self.n_cuts.data_ptr() + 8 * np.arange(n_jobs, dtype=np.uint64)
+        t["algo"] = algos
+        t["window"] = windows
+        t["max_chunk"] = maxc
+        self.host_jobs = t
+        self.jobs = torch.from_numpy(t.view(np.uint8).copy()).to(dev)
+        self.n_jobs = n_jobs
+        self.total_bytes = int(lengths.sum())
+
+    def run(self, stream=None):
+        """cdc_chunk_batch on the device job table (asynchronous)."""
+        _check(lib().cdc_chunk_batch(ctypes.c_void_p(self.jobs.data_ptr()),
+                                     self.n_jobs, _stream(stream)))
+
+    def run_each(self, stream=None):
+        """One cdc_chunk call per job (the plain path; asynchronous)."""
+        rc = lib().cdc_chunk_each(self.host_jobs.ctypes.data, self.n_jobs,
+                                  _stream(stream))
+        if rc != 0:
+            _check(rc)
+
+    def statuses(self):
+        return self.jobs.cpu().numpy().view(JOB_DTYPE)["status"].copy()
+
+    def result(self, j, n_cuts_host=None):
+        """Cut offsets of job j (int64 device tensor)."""
+        k = int(self.n_cuts[j].item()) if n_cuts_host is None else int(n_cuts_host[j])
+        b = int(self.cut_base[j])
+        return self.cuts[b:b + k]
 
 
 def release():

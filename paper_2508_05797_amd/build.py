@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcdc.so")
-SOURCES = ["chain_kernels.hip", "maxp_kernels.hip", "cdc_api.cpp"]
+SOURCES = ["chain_kernels.hip", "maxp_kernels.hip", "batch_kernels.hip",
+           "cdc_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -90,10 +90,9 @@ struct Workspace {
     EventMarks marks;
     void* dev = nullptr;
     size_t cap = 0;
-    // reservation for batches (bytes, jobs, minimum window)
-    size_t res_bytes = 0;
+    // reservation for batches
     uint32_t res_jobs = 0;
-    uint32_t res_min_w = 1;
+    BatchCaps res_caps{};
 };
 
 std::mutex g_mu;
@@ -205,6 +204,65 @@ ChainWs chain_ws(void* base, const Layout& L) {
     return w;
 }
 
+// Upper bounds of a batch of at most T bytes in J jobs with windows >= wmin
+// and maximum chunks <= mmax: every job is split into segments of its
+// algorithm's length, and its slots per segment are bounded as in
+// slots_per_segment (the chain and the MAXP bounds are added, since a batch
+// may mix them).
+BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
+    BatchCaps c{};
+    c.seg_chain = g_segment_bytes ? g_segment_bytes : kChainSegment;
+    c.seg_maxp = g_segment_bytes ? g_segment_bytes : kMaxpSegment;
+    c.max_chunk_limit = kMaxChunkLimit;
+    const uint64_t it_chain = T / c.seg_chain + J;
+    const uint64_t it_maxp = T / c.seg_maxp + J;
+    c.items = std::max(it_chain, it_maxp);
+    c.slots = it_chain * ((c.seg_chain + mmax) / (wmin + 1) + 2) +
+              it_maxp * ((c.seg_maxp + kTile) / (wmin + 1) + 2);
+    const uint32_t blog = maxp_blog((uint32_t)std::min<uint64_t>(wmin, 1u << 30));
+    c.blocks = blog ? (T / kTile + J + 1) * ((uint64_t)kTile >> blog) : 0;
+    return c;
+}
+
+struct BatchLayout {
+    size_t err, nitems, jd, items, meta, spec, fix, front, fmeta, bpos, bmax,
+        total;
+};
+
+BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
+    BatchLayout L;
+    size_t off = 0;
+    L.err = off;    off += 256;
+    L.nitems = off; off += 256;
+    L.jd = off;     off = align_up(off + n_jobs * sizeof(JobDesc), 256);
+    L.items = off;  off = align_up(off + c.items * sizeof(Item), 256);
+    L.meta = off;   off = align_up(off + c.items * sizeof(SegMeta), 256);
+    L.spec = off;   off = align_up(off + c.slots * 4, 256);
+    L.fix = off;    off = align_up(off + c.slots * 4, 256);
+    L.front = off;  // batches speculate without the front
+    L.fmeta = off;
+    L.bpos = off;   off = align_up(off + c.blocks * 8, 256);
+    L.bmax = off;   off = align_up(off + c.blocks, 256);
+    L.total = off;
+    return L;
+}
+
+// Bytes a single-buffer call needs.
+size_t single_need(uint32_t algo, uint64_t n, uint32_t w, uint32_t M,
+                   uint64_t shift) {
+    const uint64_t S = choose_segment(algo, n);
+    const uint64_t nseg = (n + S - 1) / S;
+    const uint64_t cap = slots_per_segment(algo, S, w, M);
+    const uint32_t blog = algo == kMaxp ? maxp_blog(w) : 0;
+    const uint64_t blocks =
+        blog ? (n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> blog) : 0;
+    return layout(nseg, nseg * cap, blocks, algo != kMaxp).total;
+}
+
+// Largest grid (in waves) the per-item kernels are launched with; they walk
+// the items grid-stride.
+constexpr uint64_t kMaxGridWaves = 16384;
+
 }  // namespace
 }  // namespace cdc
 
@@ -309,22 +367,24 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
 }
 
 int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
-                uint32_t min_window) {
+                uint32_t min_window, uint32_t max_chunk) {
     t_last_error.clear();
-    if (min_window == 0 || max_jobs == 0) return CDC_EINVAL;
+    if (min_window == 0 || max_jobs == 0 || max_chunk < min_window + 1ull ||
+        max_chunk > kMaxChunkLimit)
+        return CDC_EINVAL;
     std::lock_guard<std::mutex> g(g_mu);
     Workspace& ws = workspace_for(stream);
-    ws.res_bytes = max_total_bytes;
+    const BatchCaps caps =
+        batch_caps(max_total_bytes, max_jobs, min_window, max_chunk);
+    size_t need = batch_layout(caps, max_jobs).total;
+    for (uint32_t algo = 0; algo < 4; algo++)
+        need = std::max(need, single_need(algo, max_total_bytes, min_window,
+                                          max_chunk, 15));
+    const int rc = ensure(ws, need, stream);
+    if (rc != CDC_OK) return rc;
     ws.res_jobs = max_jobs;
-    ws.res_min_w = min_window;
-    // single-buffer calls of up to max_total_bytes with windows >= min_window
-    const uint64_t S = kMinSeg;
-    const uint64_t nseg = (max_total_bytes + S - 1) / S + max_jobs;
-    const uint64_t cap = (S + kMaxChunkLimit) / ((uint64_t)min_window + 1) + 2;
-    const uint64_t slots = std::min<uint64_t>(nseg * cap,
-                                              max_total_bytes / (min_window + 1) + 4 * nseg);
-    const Layout L = layout(nseg, slots, max_total_bytes / 16 + 64 * nseg, true);
-    return ensure(ws, L.total, stream);
+    ws.res_caps = caps;
+    return CDC_OK;
 }
 
 void cdc_release(void) {
@@ -342,11 +402,85 @@ void cdc_release(void) {
 }
 
 int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
-    (void)jobs;
-    (void)n_jobs;
-    (void)stream;
-    t_last_error = "batch path not built yet";
-    return CDC_ENOTSUP;
+    t_last_error.clear();
+    if (!jobs || n_jobs == 0) {
+        t_last_error = "invalid argument";
+        return CDC_EINVAL;
+    }
+    std::unique_lock<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    BatchCaps caps = ws.res_caps;
+    if (ws.res_jobs < n_jobs) {
+        // No reservation covers this batch: read the descriptors back to size
+        // the workspace (not possible while the stream is being captured).
+        if (capturing(stream)) {
+            t_last_error = "batch needs cdc_reserve before stream capture";
+            return CDC_ENOMEM;
+        }
+        std::vector<cdc_job> h(n_jobs);
+        hipError_t e = hipMemcpyAsync(h.data(), jobs, n_jobs * sizeof(cdc_job),
+                                      hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) { set_error("reading job descriptors", e); return CDC_EHIP; }
+        uint64_t T = 0, wmin = ~0ull, mmax = 1;
+        for (const cdc_job& q : h) {
+            T += q.n;
+            if (q.window >= 1) wmin = std::min<uint64_t>(wmin, q.window);
+            mmax = std::max<uint64_t>(mmax, std::min<uint64_t>(q.max_chunk, kMaxChunkLimit));
+        }
+        if (wmin == ~0ull) wmin = 1;
+        caps = batch_caps(T, n_jobs, wmin, mmax);
+        const int rc = ensure(ws, batch_layout(caps, n_jobs).total, stream);
+        if (rc != CDC_OK) return rc;
+    }
+    const BatchLayout L = batch_layout(caps, n_jobs);
+    if (L.total > ws.cap) {
+        t_last_error = "batch does not fit the reserved workspace";
+        return CDC_ENOMEM;
+    }
+    JobDesc* jd = at<JobDesc>(ws.dev, L.jd);
+    Item* items = at<Item>(ws.dev, L.items);
+    uint32_t* nitems = at<uint32_t>(ws.dev, L.nitems);
+    hipError_t e = launch_plan(const_cast<cdc_job*>(jobs), n_jobs, caps, jd,
+                               items, nitems, stream);
+    if (e != hipSuccess) { set_error("plan launch", e); return CDC_EHIP; }
+    Plan P{};
+    P.jobs = jd;
+    P.items = items;
+    P.n_items = nitems;
+    const uint32_t grid_waves = (uint32_t)std::min<uint64_t>(caps.items, kMaxGridWaves);
+    ws.marks.level = g_profile_level;
+    Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
+    ChainWs cw;
+    cw.meta = at<SegMeta>(ws.dev, L.meta);
+    cw.spec = at<uint32_t>(ws.dev, L.spec);
+    cw.fix = at<uint32_t>(ws.dev, L.fix);
+    cw.front = at<uint32_t>(ws.dev, L.front);
+    cw.fmeta = at<FrontMeta>(ws.dev, L.fmeta);
+    cw.err = at<uint32_t>(ws.dev, L.err);
+    const int wpb = g_waves_per_block;
+    e = launch_ram_ae(P, grid_waves, n_jobs, nullptr, cw, wpb, stream, mk);
+    if (e == hipSuccess)
+        e = launch_maxp(P, grid_waves, n_jobs, nullptr, cw.meta, cw.spec,
+                        at<uint8_t>(ws.dev, L.bmax), at<int64_t>(ws.dev, L.bpos),
+                        cw.err, wpb, caps.blocks != 0, stream, mk);
+    if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
+    return CDC_OK;
+}
+
+int cdc_chunk_each(cdc_job* host_jobs, uint32_t n_jobs, hipStream_t stream) {
+    if (!host_jobs) return CDC_EINVAL;
+    int first_error = CDC_OK;
+    for (uint32_t j = 0; j < n_jobs; j++) {
+        cdc_job& q = host_jobs[j];
+        const cdc_params p{q.window, q.max_chunk, 0, 0};
+        const int rc = cdc_chunk((cdc_algo)q.algo, &p, q.data, q.n,
+                                 q.cut_offsets, q.n_cuts, stream);
+        q.status = rc;
+        if (rc == CDC_EHIP) return rc;
+        if (rc != CDC_OK && first_error == CDC_OK) first_error = rc;
+    }
+    return first_error;
 }
 
 int cdc_set_profiling(int level) {

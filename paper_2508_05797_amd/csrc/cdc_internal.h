@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <hip/hip_runtime.h>
 
+#include "cdc.h"
+
 namespace cdc {
 
 constexpr int kWave = 64;          // lanes per wavefront on CDNA
@@ -91,6 +93,13 @@ struct Plan {
 // Flags raised on the device (workspace word) when a bound was violated.
 enum : uint32_t { kErrOverflow = 1u };
 
+// Capacity of a batch workspace and the planning constants.
+struct BatchCaps {
+    uint64_t items, slots, blocks;
+    uint64_t seg_chain, seg_maxp;
+    uint64_t max_chunk_limit;
+};
+
 // Host-side event marks around kernels (tracing); nullptr when off.
 struct Marks {
     virtual void begin(const char* name, int level, hipStream_t st) = 0;
@@ -118,6 +127,9 @@ hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                        uint32_t* err, int waves_per_block, bool any_blocks,
                        hipStream_t st, Marks* marks);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st);
+hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
+                       JobDesc* jd, Item* items, uint32_t* n_items,
+                       hipStream_t st);
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 
 }  // namespace cdc

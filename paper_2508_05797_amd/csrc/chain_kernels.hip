@@ -651,31 +651,34 @@ __device__ FixOutcome resolve_segment(const JobView& J, uint32_t seg,
 
 // ------------------------------------------------------------ kernels
 
+// Per-item kernels walk the items grid-stride, one wave per item.
 template <bool RAM, bool INV>
 __global__ __launch_bounds__(256) void k_spec(Plan P, ChainWs ws) {
     __shared__ WaveLds lds[4];
-    JobView J;
-    uint32_t seg;
-    const uint32_t wid = wave_global_id();
-    if (!item_of(P, wid, J, seg) || !J.ok) return;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    if (J.algo != want) return;
-    speculate<RAM, INV>(J, seg, wid, ws, lds[threadIdx.x / kWave]);
+    const uint32_t count = item_count(P);
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
+        speculate<RAM, INV>(J, seg, wid, ws, lds[threadIdx.x / kWave]);
+    }
 }
 
 template <bool RAM, bool INV>
 __global__ __launch_bounds__(64) void k_fix(Plan P, ChainWs ws) {
     __shared__ SoloLds lds[1];
-    JobView J;
-    uint32_t seg;
-    const uint32_t wid = wave_global_id();
-    if (!item_of(P, wid, J, seg) || !J.ok) return;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    if (J.algo != want) return;
-    // segment 0 starts the chain; others assume the previous main exit
-    const int64_t entry =
-        seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
-    resolve_segment<RAM, INV>(J, seg, wid, entry, ws, lds[0]);
+    const uint32_t count = item_count(P);
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
+        // segment 0 starts the chain; others assume the previous main exit
+        const int64_t entry =
+            seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
+        resolve_segment<RAM, INV>(J, seg, wid, entry, ws, lds[0]);
+    }
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x <= 1024).
@@ -695,24 +698,13 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
     return ex;
 }
 
-// Resolve one RAM / AE job (one block per job): segments whose true entry
+// Resolve one RAM / AE job with the whole block: segments whose true entry
 // is not the previous main exit are re-run in order by wave 0; then output
 // offsets are assigned.
 template <bool RAM, bool INV>
-__global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
-                                                 const uint32_t* n_jobs_d,
-                                                 ChainWs ws) {
-    __shared__ SoloLds lds[1];
-    __shared__ uint64_t sh[256];
-    __shared__ uint32_t nm_list[256];
-    __shared__ uint32_t nm_count;
-    __shared__ int64_t carry_x;
-    const uint32_t job = blockIdx.x;
-    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
-    if (job >= n_jobs) return;
-    JobView J = view(P.jobs ? P.jobs[job] : P.one);
-    const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    if (!J.ok || J.algo != want) return;
+__device__ void resolve_job(const JobView& J, const ChainWs& ws, SoloLds& lds0,
+                            uint64_t* sh, uint32_t* nm_list,
+                            uint32_t& nm_count, int64_t& carry_x) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     SegMeta* M0 = ws.meta + J.item0;
     const bool leader = tid < kWave;
@@ -758,7 +750,7 @@ __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
                         continue;
                     }
                     const FixOutcome o = resolve_segment<RAM, INV>(
-                        J, k2, J.item0 + k2, x, ws, lds[0]);
+                        J, k2, J.item0 + k2, x, ws, lds0);
                     const int64_t mexit = uni64((int64_t)M0[k2].exit);
                     x = (o.exit == mexit) ? -1 : o.exit;
                     k2++;
@@ -781,12 +773,30 @@ __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
     if (tid == 0) *J.n_cuts = carry;
 }
 
+// Resolve RAM / AE jobs, one block per job (grid-stride over jobs).
+template <bool RAM, bool INV>
+__global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
+                                                 const uint32_t* n_jobs_d,
+                                                 ChainWs ws) {
+    __shared__ SoloLds lds[1];
+    __shared__ uint64_t sh[256];
+    __shared__ uint32_t nm_list[256];
+    __shared__ uint32_t nm_count;
+    __shared__ int64_t carry_x;
+    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
+    for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
+        JobView J = view(P.jobs ? P.jobs[job] : P.one);
+        const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
+        if (J.ok && J.algo == want && J.n > 0)
+            resolve_job<RAM, INV>(J, ws, lds[0], sh, nm_list, nm_count, carry_x);
+        __syncthreads();
+    }
+}
+
+
 // Copy one segment's resolved cuts: its fix-up cuts, then its pieces.
-__global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
-    JobView J;
-    uint32_t seg;
-    const uint32_t wid = wave_global_id();
-    if (!item_of(P, wid, J, seg) || !J.ok || J.algo == kMaxp) return;
+__device__ void emit_segment(const JobView& J, uint32_t seg, uint32_t wid,
+                             const ChainWs& ws) {
     const SegMeta& m = ws.meta[wid];
     const uint64_t a = (uint64_t)seg * (uint64_t)J.seg;
     const uint64_t o = (uint64_t)uni64((int64_t)m.out);
@@ -812,6 +822,16 @@ __global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
+    const uint32_t count = item_count(P);
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo == kMaxp) continue;
+        emit_segment(J, seg, wid, ws);
+    }
+}
+
 // ------------------------------------------------------------ launches
 
 #define CDC_LAUNCH(MK, LVL, NAME, ...)                 \
@@ -830,8 +850,9 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
     CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV>), grid, blk, 0, st, P, ws);
     CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV>), dim3(items_upper),
                dim3(kWave), 0, st, P, ws);
-    CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>), dim3(jobs_upper),
-               dim3(256), 0, st, P, jobs_upper, n_jobs_d, ws);
+    CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
+               dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
+               n_jobs_d, ws);
 }
 
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,

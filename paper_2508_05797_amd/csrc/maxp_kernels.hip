@@ -62,13 +62,8 @@ __device__ void block_summaries(const uint4& v, int64_t tp, int64_t n,
     }
 }
 
-__global__ __launch_bounds__(256) void k_maxp_blocks(Plan P, uint8_t* bmax, int64_t* bpos,
-                              uint32_t* err) {
-    JobView J;
-    uint32_t seg;
-    const uint32_t wid = wave_global_id();
-    if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp || J.blog == 0)
-        return;
+__device__ void maxp_blocks_item(const JobView& J, uint32_t seg, uint8_t* bmax,
+                                 int64_t* bpos) {
     Source src;
     src.init(J.data, (uint64_t)J.n);
     // Tiles owned by this segment: those whose first position lies in
@@ -96,6 +91,20 @@ __global__ __launch_bounds__(256) void k_maxp_blocks(Plan P, uint8_t* bmax, int6
             case 9: block_summaries<32>(v, tp, J.n, bm, bp, beta0); break;
             default: block_summaries<64>(v, tp, J.n, bm, bp, beta0); break;
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_maxp_blocks(Plan P, uint8_t* bmax,
+                                                     int64_t* bpos,
+                                                     uint32_t* err) {
+    const uint32_t count = item_count(P);
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp ||
+            J.blog == 0)
+            continue;
+        maxp_blocks_item(J, seg, bmax, bpos);
     }
 }
 
@@ -137,12 +146,10 @@ __device__ bool maxp_verify(const JobView& J, const uint8_t* bm, int64_t shift,
 // Candidates of one segment, in increasing order, relative to the segment
 // start a (positions in [a, b) for the direct path; for the block path, the
 // unique maxima of the blocks whose summaries this segment wrote).
-__global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax, const int64_t* bpos,
-                              SegMeta* meta, uint32_t* cand, uint32_t* err) {
-    JobView J;
-    uint32_t seg;
-    const uint32_t wid = wave_global_id();
-    if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp) return;
+__device__ void maxp_verify_item(const JobView& J, uint32_t seg, uint32_t wid,
+                                 const uint8_t* bmax, const int64_t* bpos,
+                                 SegMeta* meta, uint32_t* cand,
+                                 uint32_t* err) {
     const int64_t a = (int64_t)seg * J.seg;
     const int64_t b = min(J.n, a + J.seg);
     uint32_t* out = cand + J.slot0 + (uint64_t)seg * J.cap;
@@ -202,6 +209,20 @@ __global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax
     if (lane_id() == 0) meta[wid].nspec = min(cnt, J.cap);
 }
 
+__global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax,
+                                                     const int64_t* bpos,
+                                                     SegMeta* meta,
+                                                     uint32_t* cand,
+                                                     uint32_t* err) {
+    const uint32_t count = item_count(P);
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp) continue;
+        maxp_verify_item(J, seg, wid, bmax, bpos, meta, cand, err);
+    }
+}
+
 // The MAXP chain over the candidates (one wave per job).  From a chunk start
 // s a candidate q is a boundary iff (q - s) mod M >= w: the forced cuts
 // s+M, s+2M, ... in between leave it at least w bytes into its chunk.  After
@@ -216,14 +237,8 @@ __device__ __forceinline__ void put_forced(uint64_t* out, uint64_t& cnt,
     cnt += (uint64_t)t;
 }
 
-__global__ __launch_bounds__(256) void k_maxp_chain(Plan P, uint32_t n_jobs_h, const uint32_t* n_jobs_d,
-                             const SegMeta* meta, const uint32_t* cand,
-                             uint32_t* err) {
-    const uint32_t job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
-    if (uni(job) >= n_jobs) return;
-    JobView J = view(P.jobs ? P.jobs[uni(job)] : P.one);
-    if (!J.ok || J.algo != kMaxp) return;
+__device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
+                               const uint32_t* cand, uint32_t* err) {
     const int64_t n = J.n, w = J.w, M = J.M;
     uint64_t* out = J.cuts;
     const uint64_t room = max_cuts_of(J);
@@ -282,6 +297,19 @@ __global__ __launch_bounds__(256) void k_maxp_chain(Plan P, uint32_t n_jobs_h, c
     if (lane_id() == 0) *J.n_cuts = cnt;
 }
 
+__global__ __launch_bounds__(256) void k_maxp_chain(Plan P, uint32_t n_jobs_h,
+                                                    const uint32_t* n_jobs_d,
+                                                    const SegMeta* meta,
+                                                    const uint32_t* cand,
+                                                    uint32_t* err) {
+    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
+    for (uint32_t job = wave_global_id(); job < n_jobs; job += wave_count()) {
+        JobView J = view(P.jobs ? P.jobs[job] : P.one);
+        if (!J.ok || J.algo != kMaxp || J.n == 0) continue;
+        maxp_chain_job(J, meta, cand, err);
+    }
+}
+
 // ------------------------------------------------------------ launches
 
 __global__ void k_set_u64(uint64_t* p, uint64_t v) {
@@ -323,7 +351,7 @@ hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                    bmax, bpos, err);
     CDC_LAUNCH(mk, any_blocks ? 2 : 1, "maxp_verify", k_maxp_verify, grid, blk,
                0, st, P, bmax, bpos, meta, cand, err);
-    const uint32_t jgrid = (jobs_upper + 3) / 4;
+    const uint32_t jgrid = min((jobs_upper + 3) / 4, 2048u);
     CDC_LAUNCH(mk, 2, "maxp_chain", k_maxp_chain, dim3(jgrid), dim3(256), 0, st,
                P, jobs_upper, n_jobs_d, meta, cand, err);
     return hipGetLastError();

@@ -197,6 +197,15 @@ __device__ __forceinline__ uint32_t wave_global_id() {
     return uni(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
 }
 
+__device__ __forceinline__ uint32_t wave_count() {
+    return gridDim.x * (blockDim.x / kWave);
+}
+
+// Number of work items of the plan (uniform).
+__device__ __forceinline__ uint32_t item_count(const Plan& P) {
+    return P.jobs == nullptr ? P.one_items : uni(*P.n_items);
+}
+
 __device__ __forceinline__ bool item_of(const Plan& P, uint32_t wid,
                                         JobView& J, uint32_t& seg) {
     if (P.jobs == nullptr) {

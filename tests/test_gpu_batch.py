@@ -1,0 +1,148 @@
+"""The batched many-file path (GPU): every job's offsets equal the oracle's
+on that buffer alone, rejected jobs do not disturb the others, the plain
+one-call-per-job path agrees, and a batch captured into a HIP graph gives
+the same result on every replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_05797_amd import binding, datagen
+
+pytestmark = pytest.mark.gpu
+
+ALGO_W = {"ram": 4096, "ae": 4096, "maxp": 2048, "ae_min": 4096}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_files(n_files, seed, max_len=3 << 20):
+    """Log-normal sizes (median 16 KiB here), uniform bytes, each file at an
+    unaligned offset inside one device buffer."""
+    rng = np.random.default_rng(seed)
+    sizes = datagen.lognormal_sizes(n_files, seed, median=16384, sigma=1.5,
+                                    lo=0, hi=max_len)
+    sizes[:3] = [0, 1, 4097]
+    gaps = rng.integers(0, 16, n_files)
+    offs = np.zeros(n_files, np.int64)
+    pos = 0
+    for i, (s, g) in enumerate(zip(sizes, gaps)):
+        pos += int(g)
+        offs[i] = pos
+        pos += int(s)
+    host = datagen.uniform(pos + 64, seed + 1)
+    # a few constant runs so the chains have lockstep stretches
+    host[1000:70000] = 7
+    return host, offs, sizes
+
+
+def check_batch(b, host, offs, sizes, algos, windows, maxc):
+    torch.cuda.synchronize()
+    nc = b.n_cuts.cpu().numpy()
+    cuts = b.cuts.cpu().numpy()
+    st = b.statuses()
+    for j in range(len(sizes)):
+        assert st[j] == 0, (j, st[j])
+        x = host[offs[j]:offs[j] + sizes[j]]
+        exp = oracle.chunk(algos[j], x, windows[j], maxc[j])
+        got = cuts[int(b.cut_base[j]):int(b.cut_base[j]) + int(nc[j])]
+        assert got.size == exp.size and np.array_equal(got.astype(np.uint64), exp), \
+            (j, algos[j], sizes[j])
+
+
+def test_batch_mixed_algorithms():
+    host, offs, sizes = make_files(300, 3)
+    rng = np.random.default_rng(5)
+    algos = [["ram", "ae", "maxp", "ae_min"][i] for i in rng.integers(0, 4, 300)]
+    windows = [ALGO_W[a] for a in algos]
+    d = torch.from_numpy(host).cuda()
+    b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+    say("case batch mixed", b.n_jobs, b.total_bytes)
+    b.run()
+    check_batch(b, host, offs, sizes, algos, windows, [65536] * 300)
+    assert binding.device_errors() == 0
+
+
+@pytest.mark.parametrize("algo", ["ram", "ae", "maxp"])
+def test_batch_equals_plain(algo):
+    host, offs, sizes = make_files(120, 11)
+    d = torch.from_numpy(host).cuda()
+    w = ALGO_W[algo]
+    b1 = binding.Batch(d, offs, sizes, algo, w, 65536)
+    b2 = binding.Batch(d, offs, sizes, algo, w, 65536)
+    say("case batch vs plain", algo)
+    b1.run()
+    b2.run_each()
+    torch.cuda.synchronize()
+    assert torch.equal(b1.n_cuts, b2.n_cuts)
+    for j in range(len(sizes)):
+        assert torch.equal(b1.result(j), b2.result(j)), j
+    check_batch(b1, host, offs, sizes, [algo] * 120, [w] * 120, [65536] * 120)
+
+
+def test_batch_rejects_invalid_jobs():
+    host, offs, sizes = make_files(40, 21)
+    d = torch.from_numpy(host).cuda()
+    windows = np.full(40, 300, np.uint32)
+    maxc = np.full(40, 4000, np.uint32)
+    windows[5] = 0          # invalid window
+    maxc[9] = 300           # max chunk not above the window
+    b = binding.Batch(d, offs, sizes, "ram", windows, maxc)
+    b.host_jobs["cut_offsets"][13] = 0
+    b.jobs = torch.from_numpy(b.host_jobs.view(np.uint8).copy()).cuda()
+    if sizes[13] == 0:
+        pytest.skip("job 13 is empty")
+    say("case batch invalid")
+    b.run()
+    torch.cuda.synchronize()
+    st = b.statuses()
+    nc = b.n_cuts.cpu().numpy()
+    for j in range(40):
+        if j in (5, 9, 13):
+            assert st[j] == -1 and nc[j] == 0, (j, st[j], nc[j])
+        else:
+            assert st[j] == 0
+            x = host[offs[j]:offs[j] + sizes[j]]
+            exp = oracle.chunk("ram", x, 300, 4000)
+            assert np.array_equal(b.result(j).cpu().numpy().astype(np.uint64), exp)
+
+
+def test_batch_graph_replay():
+    """Capture one batched call per algorithm into a HIP graph after a
+    reservation, replay it several times with eager work in between, and
+    check every replay; then change the descriptors' data and replay."""
+    host, offs, sizes = make_files(200, 31)
+    d = torch.from_numpy(host).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        binding.reserve(int(sizes.sum()) + (1 << 20), 256, 2048, 65536, stream=s)
+        bs = [binding.Batch(d, offs, sizes, a, ALGO_W[a], 65536)
+              for a in ("ram", "ae", "maxp")]
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for b in bs:
+                b.run(stream=s)
+    for rep in range(3):
+        for b in bs:
+            b.n_cuts.zero_()
+            b.cuts.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("case graph replay", rep)
+        for b, a in zip(bs, ("ram", "ae", "maxp")):
+            check_batch(b, host, offs, sizes, [a] * 200, [ALGO_W[a]] * 200,
+                        [65536] * 200)
+        _ = (d.float().sum()).item()      # unrelated eager work
+    # new bytes under the same descriptors
+    host2 = datagen.uniform(host.size, 99)
+    d.copy_(torch.from_numpy(host2).cuda())
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for b, a in zip(bs, ("ram", "ae", "maxp")):
+        check_batch(b, host2, offs, sizes, [a] * 200, [ALGO_W[a]] * 200,
+                    [65536] * 200)
