@@ -1,21 +1,33 @@
-"""Benchmark: chunk-boundary finding on the 1 GiB mixed stream (MI355X).
+"""Benchmark of the chunk-boundary path on one MI355X.
 
-One step chunks the 1 GiB stream of 64 KiB blocks (50% uniform random, 30%
-Zipf text, 20% constant runs) with RAM (w=4096), AE-Max (w=4096) and MAXP
-(w=2048 each side), max chunk 64 KiB: the whole hot path, three times over
-the same resident bytes.  ``value`` is bytes chunked per second over the
-timed steps (GB = 1e9 B); the inputs are in HBM before timing starts.
+Three legs, all on seeded synthetic data resident in HBM before timing:
 
-Also reported:
-  * roofline: the dominant kernel's algorithmic bytes (the stream, read once)
-    over its average duration from HIP events on the launch stream, against
-    the 8 TB/s HBM peak; traffic from rocprofv3 FETCH_SIZE / WRITE_SIZE
-    counters when they were taken on the current kernel source;
-  * cpu_baseline: the scalar oracle on this host, single thread, on the same
-    stream (whose cuts also check the GPU's, bit for bit);
-  * per-algorithm GB/s.
+  stream  (the headline ``value``) one step chunks a 1 GiB stream of 64 KiB
+          blocks (50% uniform random, 30% Zipf(1.1) text over 64 symbols,
+          20% constant runs) with RAM (w=4096), AE-Max (w=4096) and MAXP
+          (w=2048 each side), max chunk 64 KiB: three passes of the whole hot
+          path over the same bytes.  value = bytes chunked per second over
+          the timed steps (GB = 1e9 B).
+  batch   20,000 files of log-normal sizes (median 64 KiB, sigma 2.0,
+          clipped to 1 KiB .. 256 MiB; uniform random bytes), each algorithm
+          as one cdc_chunk_batch, tuned by cdc_autotune and captured in a HIP
+          graph, against one cdc_chunk call per file (the plain path).
+  serve   open-loop Poisson arrivals of requests (sizes as the batch leg,
+          algorithm uniform over RAM / AE / MAXP, bytes at random places of
+          the resident batch buffer) at 25 / 50 / 90 % of the measured
+          batched peak, served by cdc_serve (admission by an HBM budget,
+          continuous batching on a stream pool): p50 / p99 latency and
+          sustained GB/s.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Also reported: the roofline of the stream leg's dominant kernel (its
+algorithmic bytes, the stream read once, over its average duration from HIP
+events on the launch stream, against the 8 TB/s HBM peak; traffic from
+rocprofv3 FETCH_SIZE / WRITE_SIZE when they were taken on the current kernel
+source), and the oracle timed on this host (cpu_baseline), whose cuts also
+check the GPU's bit for bit.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--legs stream,batch,serve] [--no-cpu]
 """
 import argparse
 import hashlib
@@ -33,7 +45,16 @@ HBM_PEAK_GBS = 8000.0
 STREAM_BLOCKS = 16384          # 16384 x 64 KiB = 1 GiB
 STREAM_SEED = 2024
 ALGOS = [("ram", 4096), ("ae", 4096), ("maxp", 2048)]
+WINDOW = dict(ALGOS)
 MAX_CHUNK = 65536
+N_FILES = 20000
+FILES_SEED = 7
+SERVE_SEED = 11
+SERVE_LOADS = (0.25, 0.5, 0.9)
+SERVE_SECONDS = 0.5            # arrivals per load level
+SERVE_BUDGET = 32 << 30        # HBM for requests in flight
+SERVE_SLOTS = 4
+SERVE_MAX_BATCH = 4096
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_05797_amd", "csrc",
                           "chain_kernels.hip")
@@ -61,62 +82,21 @@ def load_traffic():
     return t
 
 
-def cpu_baseline(x, gpu_cuts):
-    import numpy as np
-    import oracle
-    total_t, exact = 0.0, True
-    for algo, w in ALGOS:
-        t0 = time.perf_counter()
-        c = oracle.chunk(algo, x, w, MAX_CHUNK)
-        total_t += time.perf_counter() - t0
-        g = gpu_cuts[algo]
-        same = (g.size == c.size) and bool(np.array_equal(g, c))
-        log("oracle %s: %d cuts, gpu %d cuts, identical=%s"
-            % (algo, c.size, g.size, same))
-        exact = exact and same
-    gbs = len(ALGOS) * x.size / total_t / 1e9
-    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "the full 1 GiB stream, each of RAM, AE, MAXP once, "
-                      "single-threaded scalar C (gcc -O2)"}, exact
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--seg", type=int, default=0,
-                    help="segment length in bytes (0: the library's choice)")
-    ap.add_argument("--no-cpu", action="store_true",
-                    help="skip the oracle leg (no cpu_baseline, no check)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
-              "and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def events():
     import torch
-    from paper_2508_05797_amd import binding, datagen
-    from paper_2508_05797_amd import build as cdc_build
+    return (torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True))
 
-    if not os.path.exists(binding.LIB_PATH):
-        cdc_build.build()
-    binding.lib()
-    binding.set_tuning(args.seg, 0)
 
-    log("generating the 1 GiB mixed stream ...")
+# ----------------------------------------------------------------- stream leg
+def stream_leg(args, binding, datagen, torch, np):
+    log("stream: generating the 1 GiB mixed stream ...")
     x, _ = datagen.mixed_stream(STREAM_BLOCKS, STREAM_SEED)
     n = x.size
     dev = torch.device("cuda:0")
     d = torch.from_numpy(x).to(dev)
-    stream = torch.cuda.current_stream()
-    bufs = {}
-    for algo, w in ALGOS:
-        bufs[algo] = (torch.empty(binding.max_cuts(n, w), dtype=torch.int64,
-                                  device=dev),
-                      torch.empty(1, dtype=torch.int64, device=dev))
+    bufs = {a: (torch.empty(binding.max_cuts(n, w), dtype=torch.int64, device=dev),
+                torch.empty(1, dtype=torch.int64, device=dev)) for a, w in ALGOS}
 
     def step(only=None):
         for algo, w in ALGOS:
@@ -125,49 +105,38 @@ def main():
             cuts, nc = bufs[algo]
             binding.chunk_into(d, algo, w, MAX_CHUNK, cuts, nc)
 
-    log("warmup ...")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-
-    # Timed region: K steps; HIP events around each call's main kernel.
+    # timed region: K steps, HIP events around each call's main kernel
     binding.set_profiling(1)
-    binding.kernel_times()                      # clear earlier records
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    binding.kernel_times()
+    t0, t1 = events()
     torch.cuda.synchronize()
     t0.record()
     for _ in range(args.steps):
         step()
     t1.record()
     torch.cuda.synchronize()
-    ms_total = t0.elapsed_time(t1)
+    ms_step = t0.elapsed_time(t1) / args.steps
     ktimes = binding.kernel_times()
     binding.set_profiling(0)
-    ms_step = ms_total / args.steps
-    value = len(ALGOS) * n / (ms_step * 1e-3) / 1e9
 
-    # Per-algorithm throughput (separate short runs of each algorithm), then
-    # one traced run per algorithm for the per-kernel breakdown.
     per_algo, breakdown = {}, {}
     for algo, _w in ALGOS:
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        e0, e1 = events()
         e0.record()
         for _ in range(args.steps):
             step(algo)
         e1.record()
         torch.cuda.synchronize()
-        per_algo[algo] = round(n / (e0.elapsed_time(e1) / args.steps * 1e-3)
-                               / 1e9, 2)
+        per_algo[algo] = round(n / (e0.elapsed_time(e1) / args.steps * 1e-3) / 1e9, 2)
         binding.set_profiling(2)
         step(algo)
         breakdown[algo] = {k: round(v[1] / max(v[0], 1), 4)
                            for k, v in binding.kernel_times().items()}
         binding.set_profiling(0)
 
-    # Roofline of the dominant kernel: the stream's bytes per launch over
-    # the launch's average duration.
     per_kernel = {k: tot / max(c, 1) for k, (c, tot) in ktimes.items()}
     dom = max(per_kernel, key=per_kernel.get)
     avg_ms = per_kernel[dom]
@@ -179,38 +148,240 @@ def main():
             "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": n,
             "traffic": (traffic or {}).get("bytes_per_launch", {}).get(dom)}
-
-    gpu_cuts = {}
-    for algo, _w in ALGOS:
-        cuts, nc = bufs[algo]
-        gpu_cuts[algo] = cuts[:int(nc.item())].cpu().numpy().astype(np.uint64)
+    gpu_cuts = {a: bufs[a][0][:int(bufs[a][1].item())].cpu().numpy().astype(np.uint64)
+                for a, _ in ALGOS}
     assert binding.device_errors() == 0
+    value = len(ALGOS) * n / (ms_step * 1e-3) / 1e9
+    del d, bufs
+    return dict(x=x, value=value, ms_step=ms_step, roof=roof, per_algo=per_algo,
+                breakdown=breakdown,
+                kernel_avg_ms={k: round(v, 4) for k, v in per_kernel.items()},
+                gpu_cuts=gpu_cuts)
 
-    cpu, exact = (None, None)
-    if not args.no_cpu:
+
+# ------------------------------------------------------------------ batch leg
+def batch_leg(binding, datagen, torch, np):
+    log("batch: generating %d files ..." % N_FILES)
+    sizes = datagen.lognormal_sizes(N_FILES, FILES_SEED)
+    host, offs = datagen.many_files(sizes, FILES_SEED)
+    total = int(sizes.sum())
+    d = torch.from_numpy(host).cuda()
+    del host
+    stream = torch.cuda.Stream()
+    out = {"files": N_FILES, "bytes": total}
+    with torch.cuda.stream(stream):
+        batches = {a: binding.Batch(d, offs[:-1], sizes, a, w, MAX_CHUNK)
+                   for a, w in ALGOS}
+        torch.cuda.synchronize()
+        tunings = {}
+        for a, _w in ALGOS:
+            t0 = time.perf_counter()
+            tunings[a] = binding.autotune(batches[a], reps=2, stream=stream)
+            log("batch: autotune %s -> %s (%.1f s)" % (a, tunings[a],
+                                                      time.perf_counter() - t0))
+        out["tuning"] = binding.get_tuning()
+        # reserve for the largest batch, then capture one call per algorithm
+        binding.reserve(total, N_FILES, min(w for _, w in ALGOS), MAX_CHUNK,
+                        stream=stream)
+        for b in batches.values():
+            b.cuts.fill_(-1)
+            b.n_cuts.fill_(-1)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for a, _w in ALGOS:
+                batches[a].run(stream=stream)
+        # replays run on the capture stream, timed with events on it
+        g.replay()
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = events()
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / reps
+    st = {a: b.statuses() for a, b in batches.items()}
+    assert all((s == 0).all() for s in st.values()), "batch job failed"
+    batched_nc = {a: b.n_cuts.clone() for a, b in batches.items()}
+    batched_cuts = {a: b.cuts.clone() for a, b in batches.items()}
+
+    # plain: one cdc_chunk per file, per algorithm, on one stream
+    with torch.cuda.stream(stream):
+        for b in batches.values():
+            b.cuts.fill_(-1)
+            b.n_cuts.fill_(-1)
+            b.run_each(stream=stream)         # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record(stream)
+        for b in batches.values():
+            b.run_each(stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    same = all(torch.equal(batched_nc[a], batches[a].n_cuts) and
+               torch.equal(batched_cuts[a], batches[a].cuts)
+               for a in batches)
+    steps_bytes = len(ALGOS) * total
+    out.update({
+        "batched_gbs": round(steps_bytes / (ms_batched * 1e-3) / 1e9, 2),
+        "plain_gbs": round(steps_bytes / (ms_plain * 1e-3) / 1e9, 2),
+        "batched_ms": round(ms_batched, 3), "plain_ms": round(ms_plain, 3),
+        "batched_identical_to_plain": bool(same),
+        "n_cuts": {a: int(batched_nc[a].sum().item()) for a in batches},
+    })
+    out["speedup"] = round(out["batched_gbs"] / out["plain_gbs"], 2)
+    log("batch:", out)
+    del g, batches
+    return d, sizes, out
+
+
+# ------------------------------------------------------------------ serve leg
+def serve_leg(pool, binding, datagen, torch, np):
+    rng = np.random.default_rng(SERVE_SEED)
+    pool_n = pool.numel()
+
+    def draw(k, seed):
+        sizes = datagen.lognormal_sizes(k, seed)
+        sizes = np.minimum(sizes, pool_n)
+        offs = (rng.random(k) * (pool_n - sizes + 1)).astype(np.int64)
+        algos = [ALGOS[i][0] for i in rng.integers(0, 3, k)]
+        wins = np.array([WINDOW[a] for a in algos])
+        return offs, sizes, algos, wins
+
+    # batched peak on the serving mix: one batch of 20,000 requests
+    offs, sizes, algos, wins = draw(N_FILES, SERVE_SEED)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = binding.Batch(pool, offs, sizes, algos, wins, MAX_CHUNK)
+        torch.cuda.synchronize()
+        binding.autotune(b, reps=2, stream=stream)
+        e0, e1 = events()
+        e0.record(stream)
+        for _ in range(3):
+            b.run(stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    peak = int(sizes.sum()) / (e0.elapsed_time(e1) / 3 * 1e-3)
+    mean_size = float(datagen.lognormal_sizes(200000, SERVE_SEED + 1).mean())
+    del b
+    out = {"batched_peak_gbs": round(peak / 1e9, 2), "budget_bytes": SERVE_BUDGET,
+           "slots": SERVE_SLOTS, "max_batch": SERVE_MAX_BATCH, "loads": []}
+    for i, load in enumerate(SERVE_LOADS):
+        rate = load * peak / mean_size
+        k = max(100, int(rate * SERVE_SECONDS))
+        offs, sizes, algos, wins = draw(k, SERVE_SEED + 10 + i)
+        arr = np.cumsum(rng.exponential(1.0 / rate, k))
+        reqs, total = binding.requests(offs, sizes, algos, wins, MAX_CHUNK, arr)
+        log("serve: load %.2f, %d requests, %.2f GB offered over %.2f s"
+            % (load, k, sizes.sum() / 1e9, arr[-1]))
+        cuts, n_cuts, lat, st, stats = binding.serve(
+            pool, reqs, total, budget_bytes=SERVE_BUDGET,
+            max_batch=SERVE_MAX_BATCH, slots=SERVE_SLOTS)
+        ok = st == 0
+        # a sample of requests: served result == the same request alone
+        nc = n_cuts.cpu().numpy()
+        same = True
+        for j in rng.choice(k, min(k, 64), replace=False):
+            q = reqs[j]
+            o, n = int(q["offset"]), int(q["n"])
+            alone = binding.chunk(pool[o:o + n], algos[j], int(q["window"]),
+                                  MAX_CHUNK)
+            cb = int(q["cut_base"])
+            same = same and torch.equal(cuts[cb:cb + int(nc[j])], alone)
+        lat_ms = lat[ok] * 1e3
+        rec = {"load": load, "requests": k,
+               "offered_gbs": round(sizes.sum() / arr[-1] / 1e9, 2),
+               "sustained_gbs": round(stats["bytes_done"] / stats["elapsed"] / 1e9, 2),
+               "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+               "failed": int((~ok).sum()), "launches": stats["launches"],
+               "max_inflight": stats["max_inflight"],
+               "max_queue": stats["max_queue"],
+               "sample_identical_to_alone": bool(same)}
+        log("serve:", rec)
+        out["loads"].append(rec)
+        del cuts, n_cuts
+    return out
+
+
+# ------------------------------------------------------------------- oracle
+def cpu_baseline(x, gpu_cuts, np):
+    import oracle
+    total_t, exact = 0.0, True
+    for algo, w in ALGOS:
+        t0 = time.perf_counter()
+        c = oracle.chunk(algo, x, w, MAX_CHUNK)
+        total_t += time.perf_counter() - t0
+        g = gpu_cuts[algo]
+        same = (g.size == c.size) and bool(np.array_equal(g, c))
+        log("oracle %s: %d cuts, gpu %d cuts, identical=%s" % (algo, c.size, g.size, same))
+        exact = exact and same
+    gbs = len(ALGOS) * x.size / total_t / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "the full 1 GiB stream of the stream leg, each of RAM, AE, "
+                      "MAXP once, single-threaded scalar C (gcc -O2)"}, exact
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--legs", default="stream,batch,serve")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (no cpu_baseline, no check)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X "
+              "and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import numpy as np
+    import torch
+    from paper_2508_05797_amd import binding, datagen
+
+    binding.lib()                 # raises if the library is not built
+    binding.set_tuning()
+
+    out = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "1 GiB stream of 64 KiB blocks: 50% uniform, "
+                                  "30% Zipf(1.1) text over 64 symbols, 20% "
+                                  "constant runs; RAM w=4096, AE w=4096, MAXP "
+                                  "w=2048, max chunk 64 KiB",
+                      "bytes": STREAM_BLOCKS * 65536,
+                      "algorithms": [a for a, _ in ALGOS],
+                      "parallelism": "single GPU"},
+           "roofline": None, "cpu_baseline": None}
+    s = None
+    if "stream" in legs:
+        s = stream_leg(args, binding, datagen, torch, np)
+        out["value"] = round(s["value"], 2)
+        out["ms_per_step"] = round(s["ms_step"], 4)
+        out["roofline"] = s["roof"]
+        out["per_algorithm_gbs"] = s["per_algo"]
+        out["kernel_avg_ms"] = s["kernel_avg_ms"]
+        out["kernel_breakdown_ms"] = s["breakdown"]
+        out["n_cuts"] = {a: int(c.size) for a, c in s["gpu_cuts"].items()}
+    pool = None
+    if "batch" in legs or "serve" in legs:
+        binding.set_tuning()
+        pool, _sizes, b = batch_leg(binding, datagen, torch, np)
+        if "batch" in legs:
+            out["batch"] = b
+    if "serve" in legs:
+        binding.set_tuning()
+        out["serve"] = serve_leg(pool, binding, datagen, torch, np)
+    if s is not None and not args.no_cpu:
         log("oracle leg ...")
-        cpu, exact = cpu_baseline(x, gpu_cuts)
-
-    out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "GB/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": "1 GiB stream of 64 KiB blocks: 50% uniform, "
-                               "30% Zipf(1.1) text over 64 symbols, 20% "
-                               "constant runs; RAM w=4096, AE w=4096, MAXP "
-                               "w=2048, max chunk 64 KiB",
-                   "bytes": n, "algorithms": [a for a, _ in ALGOS],
-                   "parallelism": "single GPU"},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "bit_exact_vs_oracle": exact,
-        "per_algorithm_gbs": per_algo,
-        "kernel_avg_ms": {k: round(v, 4) for k, v in per_kernel.items()},
-        "kernel_breakdown_ms": breakdown,
-        "n_cuts": {a: int(c.size) for a, c in gpu_cuts.items()},
-    }
+        out["cpu_baseline"], out["bit_exact_vs_oracle"] = cpu_baseline(
+            s["x"], s["gpu_cuts"], np)
     print(json.dumps(out), flush=True)
 
 

@@ -155,14 +155,44 @@ const char* cdc_status_string(int status);
 const char* cdc_last_error(void);
 
 /*
- * Tuning knobs: bytes per segment of the segment-parallel chain search
- * (16 .. 2^28), waves per workgroup (1 .. 4), and whether RAM / AE
- * speculation also runs a front of extra walkers near each segment start
- * (nonzero: on).  0 restores the built-in choice.  They change only speed,
- * never the offsets.  Returns CDC_OK or CDC_EINVAL.
+ * Tuning knobs.  They change only speed, never the offsets.
+ *   chain_segment    bytes per segment of the segment-parallel chain search
+ *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 1 MiB);
+ *   maxp_segment     bytes per MAXP work item (16 .. 2^28; 0: 64 KiB);
+ *   waves_per_block  waves per workgroup (1 .. 4; 0: 4);
+ *   front_walkers    nonzero: RAM / AE speculation also runs a front of extra
+ *                    walkers near each segment start (single-buffer calls).
+ * A reservation (cdc_reserve) keeps the segment lengths it was made with.
  */
-int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block,
-                   uint32_t front_walkers);
+typedef struct {
+    uint64_t chain_segment;
+    uint64_t maxp_segment;
+    uint32_t waves_per_block;
+    uint32_t front_walkers;
+} cdc_tuning;
+
+/* Set the process-wide tuning (null: the built-in choice).  Returns CDC_OK
+ * or CDC_EINVAL. */
+int cdc_set_tuning(const cdc_tuning* t);
+
+/* The tuning in effect, with built-in choices filled in.  CDC_OK or
+ * CDC_EINVAL (null). */
+int cdc_get_tuning(cdc_tuning* t);
+
+/*
+ * Autotune for a batch: time the batch (jobs: DEVICE descriptors as for
+ * cdc_chunk_batch) under a grid of segment lengths and waves per workgroup,
+ * one knob at a time, `reps` timed runs per candidate on `stream`, then set
+ * the fastest tuning and reserve the stream's workspace for this batch
+ * (so it can be captured next).  The batch's outputs are written (with the
+ * same values) by the trial runs.  Results are remembered per (device,
+ * job count, total bytes, windows, algorithms) in the process: tuning the
+ * same shape again only applies the remembered choice.  Synchronises;
+ * not for use under capture.  chosen (host, may be null) receives the
+ * choice.  Returns CDC_OK, CDC_EINVAL, CDC_ENOMEM or CDC_EHIP.
+ */
+int cdc_autotune(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream,
+                 uint32_t reps, cdc_tuning* chosen);
 
 /*
  * Kernel timing (tracing).  level 0: off; 1: HIP events around the main

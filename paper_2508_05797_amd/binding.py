@@ -29,6 +29,16 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("chain_segment", ctypes.c_uint64),
+                ("maxp_segment", ctypes.c_uint64),
+                ("waves_per_block", ctypes.c_uint32),
+                ("front_walkers", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Job(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_uint64),
                 ("cut_offsets", ctypes.c_void_p), ("n_cuts", ctypes.c_void_p),
@@ -67,7 +77,11 @@ def lib():
         L.cdc_last_error.restype = ctypes.c_char_p
         L.cdc_last_error.argtypes = []
         L.cdc_set_tuning.restype = _I
-        L.cdc_set_tuning.argtypes = [_U64, _U32, _U32]
+        L.cdc_set_tuning.argtypes = [_V]
+        L.cdc_get_tuning.restype = _I
+        L.cdc_get_tuning.argtypes = [_V]
+        L.cdc_autotune.restype = _I
+        L.cdc_autotune.argtypes = [_V, _U32, _V, _U32, _V]
         L.cdc_set_profiling.restype = _I
         L.cdc_set_profiling.argtypes = [_I]
         L.cdc_kernel_times.restype = _I
@@ -76,6 +90,8 @@ def lib():
                                        ctypes.POINTER(ctypes.c_double), _I]
         L.cdc_check_device_errors.restype = _I
         L.cdc_check_device_errors.argtypes = [_V]
+        L.cdc_serve.restype = _I
+        L.cdc_serve.argtypes = [_V, _U64, _V, _V, _V, _U32, _V, _V, _V, _V]
         _lib = L
     return _lib
 
@@ -123,8 +139,29 @@ def chunk(data, algo, window, max_chunk, stream=None):
     return cuts[:int(n_cuts.item())]
 
 
-def set_tuning(segment_bytes=0, waves_per_block=0, front_walkers=0):
-    _check(lib().cdc_set_tuning(segment_bytes, waves_per_block, front_walkers))
+def set_tuning(segment_bytes=0, waves_per_block=0, front_walkers=0,
+               maxp_segment=None):
+    """Segment bytes for the chain search (and for MAXP unless maxp_segment
+    is given), waves per workgroup, front walkers; 0 = built-in."""
+    t = Tuning(segment_bytes, segment_bytes if maxp_segment is None else maxp_segment,
+               waves_per_block, front_walkers)
+    _check(lib().cdc_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning():
+    t = Tuning()
+    _check(lib().cdc_get_tuning(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def autotune(batch, reps=2, stream=None):
+    """cdc_autotune on a Batch's device descriptors; returns the chosen
+    tuning (now in effect, with the stream's workspace reserved)."""
+    t = Tuning()
+    _check(lib().cdc_autotune(ctypes.c_void_p(batch.jobs.data_ptr()),
+                              batch.n_jobs, _stream(stream), reps,
+                              ctypes.byref(t)))
+    return t.as_dict()
 
 
 def device_errors(stream=None):
@@ -223,6 +260,74 @@ class Batch:
         k = int(self.n_cuts[j].item()) if n_cuts_host is None else int(n_cuts_host[j])
         b = int(self.cut_base[j])
         return self.cuts[b:b + k]
+
+
+REQUEST_DTYPE = np.dtype([("offset", "<u8"), ("n", "<u8"), ("cut_base", "<u8"),
+                          ("algo", "<u4"), ("window", "<u4"),
+                          ("max_chunk", "<u4"), ("reserved", "<u4"),
+                          ("arrival", "<f8")])
+assert REQUEST_DTYPE.itemsize == 48
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32),
+                ("slots", ctypes.c_uint32), ("min_window", ctypes.c_uint32),
+                ("max_chunk", ctypes.c_uint32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("elapsed", ctypes.c_double), ("launches", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("bytes_done", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32)]
+
+
+def requests(offsets, sizes, algos, windows, max_chunk, arrivals):
+    """Request table (host) with each request's output area laid out
+    back to back; returns (table, total offset slots)."""
+    n = len(sizes)
+    r = np.zeros(n, REQUEST_DTYPE)
+    r["offset"] = offsets
+    r["n"] = sizes
+    r["algo"] = [algo_id(a) for a in algos]
+    r["window"] = windows
+    r["max_chunk"] = max_chunk
+    r["arrival"] = arrivals
+    w = r["window"].astype(np.uint64)
+    sz = r["n"]
+    room = np.where(sz > 0, (sz - 1) // np.maximum(w + 1, 2) + 1, 0)
+    room = np.maximum(room, 1).astype(np.uint64)
+    base = np.zeros(n + 1, np.uint64)
+    np.cumsum(room, out=base[1:])
+    r["cut_base"] = base[:-1]
+    return r, int(base[-1])
+
+
+def serve(pool, reqs, total_slots, budget_bytes=0, max_batch=1024, slots=4,
+          min_window=None, max_chunk=None):
+    """Run the request loop (cdc_serve) over ``reqs`` (REQUEST_DTYPE, host),
+    whose bytes are in the uint8 device tensor ``pool``.  Returns
+    (cuts, n_cuts, latency, status, stats): cuts/n_cuts int64 device tensors,
+    latency (seconds) and status host arrays, stats a dict."""
+    assert pool.dtype == torch.uint8 and pool.is_cuda and pool.is_contiguous()
+    reqs = np.ascontiguousarray(reqs, REQUEST_DTYPE)
+    n = len(reqs)
+    cuts = torch.empty(max(total_slots, 1), dtype=torch.int64, device=pool.device)
+    n_cuts = torch.full((n,), -1, dtype=torch.int64, device=pool.device)
+    lat = np.zeros(n, np.float64)
+    st = np.zeros(n, np.int32)
+    cfg = ServeConfig(budget_bytes, max_batch, slots,
+                      int(reqs["window"].min()) if min_window is None else min_window,
+                      int(reqs["max_chunk"].max()) if max_chunk is None else max_chunk)
+    stats = ServeStats()
+    torch.cuda.synchronize()          # the pool and outputs are ready
+    rc = lib().cdc_serve(ctypes.c_void_p(pool.data_ptr()), pool.numel(),
+                         ctypes.c_void_p(cuts.data_ptr()),
+                         ctypes.c_void_p(n_cuts.data_ptr()),
+                         reqs.ctypes.data, n, ctypes.byref(cfg), lat.ctypes.data,
+                         st.ctypes.data, ctypes.byref(stats))
+    _check(rc)
+    return cuts, n_cuts, lat, st, {f: getattr(stats, f) for f, _ in ServeStats._fields_}
 
 
 def release():

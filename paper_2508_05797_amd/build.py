@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcdc.so")
 SOURCES = ["chain_kernels.hip", "maxp_kernels.hip", "batch_kernels.hip",
-           "cdc_api.cpp"]
+           "cdc_api.cpp", "serve.cpp", "autotune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

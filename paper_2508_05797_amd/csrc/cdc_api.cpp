@@ -29,8 +29,9 @@ void set_error(const char* what, hipError_t e) {
     t_last_error = buf;
 }
 
-// Tuning (speed only; never changes the offsets).
-uint64_t g_segment_bytes = 0;
+// Tuning (speed only; never changes the offsets).  0 = built-in choice.
+uint64_t g_chain_segment = 0;
+uint64_t g_maxp_segment = 0;
 int g_waves_per_block = 4;
 uint32_t g_front = 0;
 
@@ -140,10 +141,12 @@ bool params_valid(uint32_t algo, uint32_t w, uint32_t M) {
            (uint64_t)M <= kMaxChunkLimit;
 }
 
+uint64_t chain_segment() { return g_chain_segment ? g_chain_segment : kChainSegment; }
+uint64_t maxp_segment() { return g_maxp_segment ? g_maxp_segment : kMaxpSegment; }
+
 uint64_t choose_segment(uint32_t algo, uint64_t n) {
-    if (g_segment_bytes) return g_segment_bytes;
     (void)n;
-    return algo == kMaxp ? kMaxpSegment : kChainSegment;
+    return algo == kMaxp ? maxp_segment() : chain_segment();
 }
 
 uint32_t maxp_blog(uint32_t w) {
@@ -211,8 +214,8 @@ ChainWs chain_ws(void* base, const Layout& L) {
 // may mix them).
 BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
     BatchCaps c{};
-    c.seg_chain = g_segment_bytes ? g_segment_bytes : kChainSegment;
-    c.seg_maxp = g_segment_bytes ? g_segment_bytes : kMaxpSegment;
+    c.seg_chain = chain_segment();
+    c.seg_maxp = maxp_segment();
     c.max_chunk_limit = kMaxChunkLimit;
     const uint64_t it_chain = T / c.seg_chain + J;
     const uint64_t it_maxp = T / c.seg_maxp + J;
@@ -264,6 +267,22 @@ size_t single_need(uint32_t algo, uint64_t n, uint32_t w, uint32_t M,
 constexpr uint64_t kMaxGridWaves = 16384;
 
 }  // namespace
+
+void drop_workspace(hipStream_t st) {
+    std::lock_guard<std::mutex> g(g_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_ws.find({dev, (uintptr_t)st});
+    if (it == g_ws.end()) return;
+    if (it->second.dev) (void)hipFree(it->second.dev);
+    for (auto& r : it->second.marks.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : it->second.marks.pool) (void)hipEventDestroy(e);
+    g_ws.erase(it);
+}
+
 }  // namespace cdc
 
 using namespace cdc;
@@ -288,15 +307,27 @@ const char* cdc_status_string(int status) {
 
 const char* cdc_last_error(void) { return t_last_error.c_str(); }
 
-int cdc_set_tuning(uint64_t segment_bytes, uint32_t waves_per_block,
-                   uint32_t front_walkers) {
-    if (segment_bytes != 0 && (segment_bytes < 16 || segment_bytes > kMaxSeg))
-        return CDC_EINVAL;
-    if (waves_per_block > 4) return CDC_EINVAL;   // kernels are built for <= 256 threads
+int cdc_set_tuning(const cdc_tuning* t) {
+    const cdc_tuning z{0, 0, 0, 0};
+    if (!t) t = &z;
+    auto bad_seg = [](uint64_t s) { return s != 0 && (s < 16 || s > kMaxSeg); };
+    if (bad_seg(t->chain_segment) || bad_seg(t->maxp_segment)) return CDC_EINVAL;
+    if (t->waves_per_block > 4) return CDC_EINVAL;   // kernels are built for <= 256 threads
     std::lock_guard<std::mutex> g(g_mu);
-    g_segment_bytes = segment_bytes;
-    g_waves_per_block = waves_per_block ? (int)waves_per_block : 4;
-    g_front = front_walkers ? 1u : 0u;
+    g_chain_segment = t->chain_segment;
+    g_maxp_segment = t->maxp_segment;
+    g_waves_per_block = t->waves_per_block ? (int)t->waves_per_block : 4;
+    g_front = t->front_walkers ? 1u : 0u;
+    return CDC_OK;
+}
+
+int cdc_get_tuning(cdc_tuning* t) {
+    if (!t) return CDC_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    t->chain_segment = chain_segment();
+    t->maxp_segment = maxp_segment();
+    t->waves_per_block = (uint32_t)g_waves_per_block;
+    t->front_walkers = g_front;
     return CDC_OK;
 }
 

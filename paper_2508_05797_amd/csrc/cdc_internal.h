@@ -132,4 +132,8 @@ hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
                        hipStream_t st);
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 
+// Free the workspace of a stream the caller is about to destroy (the
+// stream must be idle).
+void drop_workspace(hipStream_t st);
+
 }  // namespace cdc

@@ -1,18 +1,19 @@
-"""The C ABI library loads and exports every function include/cdc.h declares
+"""The C ABI library loads and exports every function include/*.h declares
 (no GPU needed: nothing is called that touches a device)."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "cdc.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_2508_05797_amd", "libcdc.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(cdc_[a-z_0-9]+)\s*\(", text)))
 
@@ -20,7 +21,8 @@ def declared_functions():
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ["cdc_chunk", "cdc_chunk_batch", "cdc_max_cuts", "cdc_reserve",
-                 "cdc_release", "cdc_status_string", "cdc_last_error"]:
+                 "cdc_release", "cdc_status_string", "cdc_last_error",
+                 "cdc_chunk_each", "cdc_autotune", "cdc_set_tuning", "cdc_serve"]:
         assert must in names
 
 
@@ -54,6 +56,17 @@ def test_host_only_entry_points():
                        ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
     assert L.cdc_chunk(0, ctypes.byref(q), None, 100, ctypes.c_void_p(1),
                        ctypes.c_void_p(1), None) == -1
-    assert L.cdc_set_tuning(8, 0, 0) == -1
-    assert L.cdc_set_tuning(0, 9, 0) == -1
-    assert L.cdc_set_tuning(0, 0, 0) == 0
+    T = binding.Tuning
+    assert L.cdc_set_tuning(ctypes.byref(T(8, 0, 0, 0))) == -1
+    assert L.cdc_set_tuning(ctypes.byref(T(0, (1 << 28) + 1, 0, 0))) == -1
+    assert L.cdc_set_tuning(ctypes.byref(T(0, 0, 9, 0))) == -1
+    assert L.cdc_set_tuning(ctypes.byref(T(4096, 1 << 16, 2, 0))) == 0
+    assert binding.get_tuning() == {"chain_segment": 4096, "maxp_segment": 65536,
+                                    "waves_per_block": 2, "front_walkers": 0}
+    assert L.cdc_set_tuning(None) == 0
+    assert binding.get_tuning() == {"chain_segment": 1 << 20, "maxp_segment": 1 << 16,
+                                    "waves_per_block": 4, "front_walkers": 0}
+    assert L.cdc_autotune(None, 1, None, 1, None) == -1
+    assert L.cdc_get_tuning(None) == -1
+    # the serving loop validates before creating streams
+    assert L.cdc_serve(None, 0, None, None, None, 0, None, None, None, None) == -1

@@ -146,3 +146,41 @@ def test_batch_graph_replay():
     for b, a in zip(bs, ("ram", "ae", "maxp")):
         check_batch(b, host2, offs, sizes, [a] * 200, [ALGO_W[a]] * 200,
                     [65536] * 200)
+
+
+def test_autotune_then_capture():
+    """The autotuner picks a tuning from its grid, reserves the workspace,
+    and the batch under that tuning (eager and captured) still equals the
+    oracle; tuning the same shape again reuses the choice."""
+    host, offs, sizes = make_files(150, 71)
+    d = torch.from_numpy(host).cuda()
+    algos = ["ram", "ae", "maxp"] * 50
+    windows = [ALGO_W[a] for a in algos]
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+            torch.cuda.synchronize()
+            say("case autotune")
+            t1 = binding.autotune(b, reps=1, stream=s)
+            assert t1["chain_segment"] in (256 << 10, 512 << 10, 1 << 20, 2 << 20, 4 << 20)
+            assert t1["maxp_segment"] in (16 << 10, 32 << 10, 64 << 10, 128 << 10, 256 << 10)
+            assert t1["waves_per_block"] in (1, 2, 4)
+            assert binding.get_tuning() == t1
+            assert binding.autotune(b, reps=1, stream=s) == t1
+            b.cuts.fill_(-1)
+            b.run(stream=s)
+            torch.cuda.synchronize()
+            check_batch(b, host, offs, sizes, algos, windows, [65536] * 150)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                b.run(stream=s)
+        for _ in range(2):
+            b.cuts.fill_(-1)
+            b.n_cuts.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            check_batch(b, host, offs, sizes, algos, windows, [65536] * 150)
+    finally:
+        binding.set_tuning()
