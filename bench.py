@@ -56,8 +56,7 @@ SERVE_BUDGET = 32 << 30        # HBM for requests in flight
 SERVE_SLOTS = 4
 SERVE_MAX_BATCH = 4096
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2508_05797_amd", "csrc",
-                          "chain_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2508_05797_amd", "csrc")
 
 
 def log(*a):
@@ -65,8 +64,13 @@ def log(*a):
 
 
 def kernel_source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of every device source (kernels and the headers they use)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
@@ -325,6 +329,22 @@ def cpu_baseline(x, gpu_cuts, np):
                       "MAXP once, single-threaded scalar C (gcc -O2)"}, exact
 
 
+def copy_calibration():
+    """A plain elementwise copy (reads 1 GiB, writes 1 GiB per launch): what
+    the FETCH_SIZE / WRITE_SIZE counters report for it scales theirs for
+    the chunking kernels."""
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(7)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(a, 1, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n,
+                      "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,12 +353,18 @@ def main():
     ap.add_argument("--legs", default="stream,batch,serve")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle leg (no cpu_baseline, no check)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy kernel three "
+                         "times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build runs on a single MI355X "
               "and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
