@@ -159,16 +159,16 @@ const char* cdc_last_error(void);
  *   chain_segment    bytes per segment of the segment-parallel chain search
  *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 1 MiB);
  *   maxp_segment     bytes per MAXP work item (16 .. 2^28; 0: 64 KiB);
- *   waves_per_block  waves per workgroup (1 .. 4; 0: 4);
- *   front_walkers    nonzero: RAM / AE speculation also runs a front of extra
- *                    walkers near each segment start (single-buffer calls).
+ *   waves_per_block  waves per workgroup of the speculation pass (1 .. 4;
+ *                    0: 4);
+ *   reserved         must be 0.
  * A reservation (cdc_reserve) keeps the segment lengths it was made with.
  */
 typedef struct {
     uint64_t chain_segment;
     uint64_t maxp_segment;
     uint32_t waves_per_block;
-    uint32_t front_walkers;
+    uint32_t reserved;
 } cdc_tuning;
 
 /* Set the process-wide tuning (null: the built-in choice).  Returns CDC_OK

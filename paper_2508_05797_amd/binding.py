@@ -33,7 +33,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("chain_segment", ctypes.c_uint64),
                 ("maxp_segment", ctypes.c_uint64),
                 ("waves_per_block", ctypes.c_uint32),
-                ("front_walkers", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -139,12 +139,11 @@ def chunk(data, algo, window, max_chunk, stream=None):
     return cuts[:int(n_cuts.item())]
 
 
-def set_tuning(segment_bytes=0, waves_per_block=0, front_walkers=0,
-               maxp_segment=None):
+def set_tuning(segment_bytes=0, waves_per_block=0, maxp_segment=None):
     """Segment bytes for the chain search (and for MAXP unless maxp_segment
-    is given), waves per workgroup, front walkers; 0 = built-in."""
+    is given) and waves per workgroup; 0 = built-in."""
     t = Tuning(segment_bytes, segment_bytes if maxp_segment is None else maxp_segment,
-               waves_per_block, front_walkers)
+               waves_per_block, 0)
     _check(lib().cdc_set_tuning(ctypes.byref(t)))
 
 

@@ -66,7 +66,6 @@ __global__ __launch_bounds__(1024) void k_plan(cdc_job* jobs, uint32_t n_jobs,
             d.w = q.window;
             d.M = q.max_chunk;
             d.ok = ok ? 1 : 0;
-            d.front = 0;
             if (ok && q.n > 0) {
                 const bool maxp = q.algo == kMaxp;
                 d.seg = maxp ? caps.seg_maxp : caps.seg_chain;

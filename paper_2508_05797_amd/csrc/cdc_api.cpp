@@ -33,7 +33,6 @@ void set_error(const char* what, hipError_t e) {
 uint64_t g_chain_segment = 0;
 uint64_t g_maxp_segment = 0;
 int g_waves_per_block = 4;
-uint32_t g_front = 0;
 
 constexpr uint64_t kMinSeg = 64 << 10;
 // Segments and chunks are at most 2^28 bytes: the chain kernels keep
@@ -177,19 +176,20 @@ T* at(void* base, size_t off) {
 }
 
 struct Layout {
-    size_t err, meta, spec, fix, front, fmeta, bmax, bpos, total;
+    size_t err, meta, spec, fix, rew, bmax, bpos, total;
 };
 
+// Workspace of one job: per item a record and, for RAM / AE, three cut
+// lists (speculative, fix-up, re-walk) of `slots / items` entries each; for
+// MAXP one candidate list and the block summaries.
 Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain) {
     Layout L;
     size_t off = 0;
-    const uint64_t fl = chain ? items * kFront : 0;
     L.err = off;   off += 256;
     L.meta = off;  off = align_up(off + items * sizeof(SegMeta), 256);
     L.spec = off;  off = align_up(off + slots * 4, 256);
     L.fix = off;   off = align_up(off + (chain ? slots * 4 : 0), 256);
-    L.front = off; off = align_up(off + fl * (kFrontCap + 1) * 4, 256);
-    L.fmeta = off; off = align_up(off + fl * sizeof(FrontMeta), 256);
+    L.rew = off;   off = align_up(off + (chain ? slots * 4 : 0), 256);
     L.bpos = off;  off = align_up(off + blocks * 8, 256);
     L.bmax = off;  off = align_up(off + blocks, 256);
     L.total = off;
@@ -201,8 +201,7 @@ ChainWs chain_ws(void* base, const Layout& L) {
     w.meta = at<SegMeta>(base, L.meta);
     w.spec = at<uint32_t>(base, L.spec);
     w.fix = at<uint32_t>(base, L.fix);
-    w.front = at<uint32_t>(base, L.front);
-    w.fmeta = at<FrontMeta>(base, L.fmeta);
+    w.rew = at<uint32_t>(base, L.rew);
     w.err = at<uint32_t>(base, L.err);
     return w;
 }
@@ -228,8 +227,7 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
 }
 
 struct BatchLayout {
-    size_t err, nitems, jd, items, meta, spec, fix, front, fmeta, bpos, bmax,
-        total;
+    size_t err, nitems, jd, items, meta, spec, fix, rew, bpos, bmax, total;
 };
 
 BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
@@ -242,8 +240,7 @@ BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
     L.meta = off;   off = align_up(off + c.items * sizeof(SegMeta), 256);
     L.spec = off;   off = align_up(off + c.slots * 4, 256);
     L.fix = off;    off = align_up(off + c.slots * 4, 256);
-    L.front = off;  // batches speculate without the front
-    L.fmeta = off;
+    L.rew = off;    off = align_up(off + c.slots * 4, 256);
     L.bpos = off;   off = align_up(off + c.blocks * 8, 256);
     L.bmax = off;   off = align_up(off + c.blocks, 256);
     L.total = off;
@@ -313,11 +310,11 @@ int cdc_set_tuning(const cdc_tuning* t) {
     auto bad_seg = [](uint64_t s) { return s != 0 && (s < 16 || s > kMaxSeg); };
     if (bad_seg(t->chain_segment) || bad_seg(t->maxp_segment)) return CDC_EINVAL;
     if (t->waves_per_block > 4) return CDC_EINVAL;   // kernels are built for <= 256 threads
+    if (t->reserved != 0) return CDC_EINVAL;
     std::lock_guard<std::mutex> g(g_mu);
     g_chain_segment = t->chain_segment;
     g_maxp_segment = t->maxp_segment;
     g_waves_per_block = t->waves_per_block ? (int)t->waves_per_block : 4;
-    g_front = t->front_walkers ? 1u : 0u;
     return CDC_OK;
 }
 
@@ -327,7 +324,7 @@ int cdc_get_tuning(cdc_tuning* t) {
     t->chain_segment = chain_segment();
     t->maxp_segment = maxp_segment();
     t->waves_per_block = (uint32_t)g_waves_per_block;
-    t->front_walkers = g_front;
+    t->reserved = 0;
     return CDC_OK;
 }
 
@@ -360,7 +357,6 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
         std::lock_guard<std::mutex> g(g_mu);
         jd.seg = choose_segment(jd.algo, n);
         wpb = g_waves_per_block;
-        jd.front = g_front;
     }
     jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
     jd.item0 = 0;
@@ -486,8 +482,7 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
     cw.meta = at<SegMeta>(ws.dev, L.meta);
     cw.spec = at<uint32_t>(ws.dev, L.spec);
     cw.fix = at<uint32_t>(ws.dev, L.fix);
-    cw.front = at<uint32_t>(ws.dev, L.front);
-    cw.fmeta = at<FrontMeta>(ws.dev, L.fmeta);
+    cw.rew = at<uint32_t>(ws.dev, L.rew);
     cw.err = at<uint32_t>(ws.dev, L.err);
     const int wpb = g_waves_per_block;
     e = launch_ram_ae(P, grid_waves, n_jobs, nullptr, cw, wpb, stream, mk);

@@ -28,51 +28,41 @@ struct JobDesc {
     uint32_t nseg;           // number of segments (work items) of this job
     uint64_t seg;            // segment length S in bytes
     uint32_t item0;          // index of the first work item of this job
-    uint32_t cap;            // cut (or candidate) slots per segment
+    uint32_t cap;            // cut (or candidate) slots per segment and list
     uint64_t slot0;          // first slot of this job in the slot arrays
     uint64_t blk0;           // first block-summary entry (MAXP)
     uint32_t blog;           // log2 of the MAXP block length (0: direct path)
-    uint32_t front;          // 1: speculate with a front of extra walkers
     int32_t ok;              // 1 if the job passed validation
 };
 
-// Speculation front: besides the main walker started at the segment start,
-// kFront walkers start at evenly spaced offsets within the first chunk's
-// length, so that a chain entering the segment anywhere there has recorded
-// walkers close on both sides and meets one of them within a few chunks.
-constexpr int kFront = 7;
-constexpr int kFrontCap = 48;             // positions kept per front walker
-constexpr int kMaxPieces = kFront + 1;    // walkers a resolved chain can visit
+// Cut lists of a RAM / AE segment (positions relative to the segment
+// start, increasing): the speculative chain from the segment start, the
+// fix-up chain from the previous segment's speculative exit, and a re-walk
+// chain from a later-known entry.
+enum : uint32_t { kListSpec = 0, kListFix = 1, kListRewalk = 2 };
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// How a front walker ended: coalesced into another walker (its id), left
-// the segment (kEndExit), or was cut off after kFrontCap positions.
-enum : uint32_t { kEndExit = 0xFE, kEndTrunc = 0xFF, kEndAlive = 0xFD };
-
-struct FrontMeta {
-    uint32_t count;          // positions stored (the first is the start)
-    uint32_t end;            // walker id it merged into, or kEnd*
-    uint32_t dpos;           // where it ended, relative to the segment start
-    uint32_t pad;
-};
-
-// A run of stored positions [lo, hi) of one walker's list (0: main walker,
-// 1..kFront: front walkers) that belongs to the resolved chain.
+// A run [lo, hi) of one list that belongs to the resolved chain.
 struct Piece {
-    uint32_t list, lo, hi, pad;
+    uint32_t list, lo, hi;
 };
 
-// Per-segment record of the speculate / fix-up / resolve passes.
+// Per-segment record of the speculate / fix-up / round / resolve passes.
+// Absolute positions are job offsets.
 struct SegMeta {
-    uint64_t exit;           // exit of the main walker (speculative exit)
-    uint64_t h;              // where the chain from the resolved entry leaves
+    uint64_t exit;           // speculative chain: first cut at or past the segment end
+    uint64_t fexit;          // fix-up chain: where it leaves (if it never met the speculative one)
+    uint64_t entry;          // entry the current resolution starts from
+    uint64_t rexit;          // current resolution: first cut at or past the segment end
+    uint64_t xo[2];          // resolved exits of the parallel rounds (double buffer)
     uint64_t out;            // offset of this segment's cuts in the output
-    uint32_t nspec;          // main-walker cuts stored
-    uint32_t nfix;           // fix-up cuts stored
-    uint32_t count;          // cuts this segment contributes
-    uint32_t merged;         // 1 if the chain met a recorded walker
+    uint32_t nspec;          // speculative cuts stored (MAXP: candidates)
+    uint32_t nfix;           // fix-up cuts stored before it met the speculative chain
+    uint32_t fms;            // speculative index the fix-up chain continues from, or kNone
+    uint32_t count;          // cuts of the current resolution
     uint32_t npieces;
-    uint32_t nfront;         // front walkers started
-    Piece pieces[kMaxPieces];
+    uint32_t pad;
+    Piece pieces[3];
 };
 
 struct Item {
@@ -110,12 +100,14 @@ struct Marks {
 // Workspace of the RAM / AE passes.
 struct ChainWs {
     SegMeta* meta;           // per item
-    uint32_t* spec;          // main-walker cuts, cap per item (job slots)
-    uint32_t* fix;           // fix-up cuts, cap per item (job slots)
-    uint32_t* front;         // kFront lists of kFrontCap+1 per item
-    FrontMeta* fmeta;        // kFront per item
+    uint32_t* spec;          // speculative cuts, cap per item (job slots)
+    uint32_t* fix;           // fix-up cuts, cap per item
+    uint32_t* rew;           // re-walk cuts, cap per item
     uint32_t* err;
 };
+
+// Parallel resolution rounds after the fix-up before the ordered pass.
+constexpr int kRounds = 2;
 
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,

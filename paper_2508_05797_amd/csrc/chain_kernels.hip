@@ -1,652 +1,798 @@
 // RAM and AE chunk chains on gfx950: speculate, fix up, resolve, emit.
 //
-// Patterns (Section 4 of the paper) as wavefront operations on a 1 KiB tile
-// (64 lanes x 16 B) staged through a per-wave LDS ring:
-//   * extreme byte search (Section 4.1): every tile gets its per-lane byte
-//     maxima (SWAR v_pk_max_u16) and the tile maximum (DPP reduction) once;
-//     a window that covers whole tiles is then one scalar max per tile, and
-//     only its two partial end tiles need a masked reduction;
-//   * range scan (Section 4.2): a tile whose maximum is below the threshold
-//     is skipped with one scalar compare; otherwise a ballot of the lane
-//     maxima finds the first candidate lane and a scalar SWAR compare of its
-//     16 bytes the exact byte.
+// The two patterns of the paper (Section 4) as wavefront operations on a
+// 1 KiB tile (64 lanes x 16 B) staged through a per-wave LDS ring:
+//   * extreme byte search (Section 4.1): each lane keeps a running maximum of
+//     its 16-byte pieces of the window (SWAR v_pk_max_u16); the 64 lane
+//     maxima are reduced (DPP) once, where the window ends; the at most two
+//     lanes that the window covers only in part are read out (readlane) and
+//     reduced on uniform values;
+//   * range scan (Section 4.2): a ballot of "lane maximum >= T" names the
+//     lanes that can hold a hit; the first one is read out and its bytes are
+//     compared with T as four SWAR words.
 // RAM (Section 2.1 "RAM"; Section 4.3) is one window maximum followed by a
-// GEQ scan; AE-Max (Section 2.1 "AE"; Section 4.3) is a chain of GT scans
-// from the current target, which visits every byte once (AE-Min runs as
-// AE-Max of the complemented bytes).
+// greater-or-equal scan; AE-Max (Section 2.1 "AE"; Section 4.3) is a chain of
+// greater-than scans from the current target, which reads every byte once
+// (AE-Min runs as AE-Max of the complemented bytes).  A walker's state
+// (chunk start, limit, position, threshold) is uniform and lives in scalar
+// registers; per tile it costs the lane maxima and a few scalar compares
+// unless a chunk boundary falls into the tile.
 //
-// The chain (cut k+1 depends on cut k) is split into segments.  In each
-// segment a main walker speculates the chain from the segment start, and
-// kFront more walkers start at evenly spaced offsets inside the first
-// chunk's length; walkers that reach the same cut coalesce (the later one
-// records where and into whom).  Two walkers on the same data meet only
-// when they pick the same boundary byte, and the gap between them performs
-// a random walk, so a lone speculative chain can stay apart from the true
-// one for a long way; with recorded walkers close on both sides, the chain
-// that really enters the segment meets one of them within a few chunks.
-// The fix-up pass runs each segment from the previous segment's main exit
-// until it meets a recorded walker, the resolve pass walks the segments in
-// order (re-running the rare ones whose true entry differs from the one the
-// fix-up assumed), and the emit pass copies the resolved cuts.
+// The chain (cut k+1 depends on cut k) is split into segments.  Speculation
+// runs one walker per segment from the segment start and records its cuts up
+// to the first one at or past the segment end (its exit).  The fix-up pass
+// runs each segment from the previous segment's speculative exit until a cut
+// lands on the speculative list (the two chains coincide from there).  A
+// segment whose fix-up never lands hands its successor an entry that the
+// fix-up did not assume; parallel rounds re-walk exactly those successors
+// (landing on either recorded list), and an ordered pass per job settles
+// what is left.  The emit pass copies every segment's resolved pieces.
 #include "wave.h"
 
 namespace cdc {
 
-constexpr int kGroup = 8;       // tiles staged per stream step (speculation)
-constexpr int kGroupSolo = 32;  // same for the lone fix-up / re-run walkers
-constexpr int kFL = kFrontCap + 1;        // entries per front list
-static_assert(kFL <= kWave, "a front list must fit one entry per lane");
-
-// ------------------------------------------------------------ tile scans
+constexpr int kGroup = 8;        // tiles staged per step (speculation)
+constexpr int kGroupSolo = 16;   // same for the lone fix-up / re-walk walkers
 
 // Positions inside the chain engine are 32-bit offsets from the segment
 // start (segments and chunks are at most 2^28 bytes, so every position a
 // walker visits fits), which keeps the walkers' compares on the scalar unit.
 
-// Largest byte in [lo, hi) clipped to the tile at tp (uniform result).
-__device__ __forceinline__ uint32_t range_max(const uint4& v, uint32_t lm,
-                                              int32_t tp, int32_t lo,
-                                              int32_t hi) {
-    const int32_t lo_t = lo - tp, hi_t = hi - tp;        // scalar
-    const int32_t lp = 16 * (int32_t)lane_id();
-    const int a = min(max(lo_t - lp, 0), 16);
-    const int b = min(max(hi_t - lp, 0), 16);
-    uint32_t x = 0;
-    if (a == 0 && b == 16)
-        x = lm;
-    else if (a < b)
-        x = lane_max16(keep_bytes(v, a, b));
-    return wave_max(x);
+// ------------------------------------------------------------ lane bytes
+
+// The 16 bytes of lane l of a tile, as uniform words.
+struct Lane16 {
+    uint32_t d0, d1, d2, d3;
+};
+
+__device__ __forceinline__ Lane16 lane_words(const uint4& v, int l) {
+    return Lane16{(uint32_t)__builtin_amdgcn_readlane((int)v.x, l),
+                  (uint32_t)__builtin_amdgcn_readlane((int)v.y, l),
+                  (uint32_t)__builtin_amdgcn_readlane((int)v.z, l),
+                  (uint32_t)__builtin_amdgcn_readlane((int)v.w, l)};
 }
 
-// 16-bit mask of the bytes of one lane (four dwords) that are >= T,
-// 1 <= T <= 255; evaluated on uniform values it runs on the scalar unit.
-__device__ __forceinline__ uint32_t geq16(uint32_t d0, uint32_t d1,
-                                          uint32_t d2, uint32_t d3, int T) {
-    const uint32_t k = (uint32_t)(256 - T) * 0x00010001u;
-    return geq_nib(d0, k) | (geq_nib(d1, k) << 4) | (geq_nib(d2, k) << 8) |
-           (geq_nib(d3, k) << 12);
+__device__ __forceinline__ uint32_t byte_of(const Lane16& q, int i) {
+    const uint32_t d = i < 4 ? q.d0 : i < 8 ? q.d1 : i < 12 ? q.d2 : q.d3;
+    return (d >> (8 * (i & 3))) & 0xFFu;
 }
 
-// Range scan: the first position j in [lo, hi), clipped to the tile, whose
-// byte is >= T (T <= 0: any byte, T > 255: none); -1 if there is none.
-__device__ __forceinline__ int32_t find_first(const uint4& v, uint32_t lm,
-                                              int32_t tp, int32_t lo,
-                                              int32_t hi, int T,
-                                              uint32_t& val) {
-    int32_t lo_t = lo - tp, hi_t = hi - tp;
-    if (lo_t < 0) lo_t = 0;
-    if (hi_t > kTile) hi_t = kTile;
-    if (lo_t >= hi_t || T > 255) return -1;
-    if (T <= 0) {
-        const uint32_t dw = __builtin_amdgcn_readlane(
-            pick_dword(v, (lo_t & 15) >> 2), lo_t >> 4);
-        val = (dw >> (8 * (lo_t & 3))) & 0xFFu;
-        return tp + lo_t;
-    }
-    const int32_t lp = 16 * (int32_t)lane_id();
-    const bool cand = lp + 16 > lo_t && lp < hi_t && (int)lm >= T;
-    uint64_t ball = __ballot(cand);
+// Largest byte among bytes [a, b) of the lane (0 if the range is empty).
+__device__ __forceinline__ uint32_t lane_range_max(const Lane16& q, int a,
+                                                   int b) {
+    const uint4 m = make_uint4(q.d0 & dword_mask(a, b, 0),
+                               q.d1 & dword_mask(a, b, 1),
+                               q.d2 & dword_mask(a, b, 2),
+                               q.d3 & dword_mask(a, b, 3));
+    return uni(lane_max16(m));
+}
+
+// High bit of every byte of x that is >= the corresponding byte of y, whose
+// bytes all equal the threshold; yl = y & 0x7F7F7F7F.  Per byte: equal top
+// bits compare by the low seven bits ((x | 0x80) - (y & 0x7F) keeps bit 7
+// exactly when x's low part is not smaller, and never borrows from the next
+// byte); different top bits compare by the top bit.
+__device__ __forceinline__ uint32_t ge_bytes(uint32_t x, uint32_t y,
+                                             uint32_t yl) {
+    const uint32_t H = 0x80808080u;
+    const uint32_t r = (x | H) - yl;
+    return ((x & ~y) | (~(x ^ y) & r)) & H;
+}
+
+// Bytes [k, 8) of a 64-bit word (all for k <= 0, none for k >= 8).
+__device__ __forceinline__ uint64_t bytes_from(int k) {
+    return k <= 0 ? ~0ull : k >= 8 ? 0ull : (~0ull << (8 * k));
+}
+// Bytes [0, k) of a 64-bit word (none for k <= 0, all for k >= 8).
+__device__ __forceinline__ uint64_t bytes_to(int k) {
+    return k >= 8 ? ~0ull : k <= 0 ? 0ull : ((1ull << (8 * k)) - 1ull);
+}
+
+// Index of the first byte >= T among bytes [a, b) of the lane, or -1
+// (0 <= T <= 255).  The lane is compared as two 64-bit SWAR words (as
+// ge_bytes, eight bytes at a time).
+__device__ __forceinline__ int lane_first_ge(const Lane16& q, int a, int b,
+                                             uint32_t T) {
+    const uint64_t H = 0x8080808080808080ull;
+    const uint64_t y = (uint64_t)(T * 0x01010101u) * 0x100000001ull;
+    const uint64_t yl = y & ~H;
+    const uint64_t x0 = ((uint64_t)q.d1 << 32) | q.d0;
+    const uint64_t x1 = ((uint64_t)q.d3 << 32) | q.d2;
+    const uint64_t r0 = (x0 | H) - yl, r1 = (x1 | H) - yl;
+    uint64_t g0 = ((x0 & ~y) | (~(x0 ^ y) & r0)) & H;
+    uint64_t g1 = ((x1 & ~y) | (~(x1 ^ y) & r1)) & H;
+    g0 &= bytes_from(a) & bytes_to(b);
+    g1 &= bytes_from(a - 8) & bytes_to(b - 8);
+    if (g0) return __builtin_ctzll(g0) >> 3;
+    if (g1) return 8 + (__builtin_ctzll(g1) >> 3);
+    return -1;
+}
+
+// Range scan: the first position j in [lo, hi) (both inside the tile at tp,
+// lo < hi) whose byte is >= T, 1 <= T <= 255; -1 if there is none.  lm holds
+// the lane maxima; *val receives the byte.
+__device__ __forceinline__ int32_t tile_find_ge(const uint4& v, uint32_t lm,
+                                                int32_t tp, int32_t lo,
+                                                int32_t hi, uint32_t T,
+                                                uint32_t& val) {
+    const int32_t lo_t = lo - tp, hi_t = hi - tp;
+    const int la = lo_t >> 4, lb = (hi_t - 1) >> 4;
+    uint64_t ball = __ballot(lm >= T);
+    ball &= (~0ull << la) & (lb >= 63 ? ~0ull : ((2ull << lb) - 1ull));
     while (ball) {
         const int f = __builtin_ctzll(ball);
         ball &= ball - 1;
-        const uint32_t d0 = __builtin_amdgcn_readlane(v.x, f);
-        const uint32_t d1 = __builtin_amdgcn_readlane(v.y, f);
-        const uint32_t d2 = __builtin_amdgcn_readlane(v.z, f);
-        const uint32_t d3 = __builtin_amdgcn_readlane(v.w, f);
-        const int32_t fp = 16 * f;
-        const int a = min(max(lo_t - fp, 0), 16);
-        const int b = min(max(hi_t - fp, 0), 16);
-        const uint32_t bits =
-            geq16(d0, d1, d2, d3, T) & ((1u << b) - 1u) & ~((1u << a) - 1u);
-        if (bits) {
-            const int bi = __builtin_ctz(bits);
-            const uint32_t dw = bi < 4 ? d0 : bi < 8 ? d1 : bi < 12 ? d2 : d3;
-            val = (dw >> (8 * (bi & 3))) & 0xFFu;
-            return tp + fp + bi;
+        const Lane16 q = lane_words(v, f);
+        const int i = lane_first_ge(q, lo_t - 16 * f, hi_t - 16 * f, T);
+        if (i >= 0) {
+            val = byte_of(q, i);
+            return tp + 16 * f + i;
         }
     }
     return -1;
 }
 
+// Largest lane maximum among lanes [l0, l1) (0 if the range is empty).
+__device__ __forceinline__ uint32_t lanes_max(uint32_t lm, int32_t l0,
+                                              int32_t l1) {
+    if (l0 >= l1) return 0;
+    if (l0 == 0 && l1 == kWave) return wave_max(lm);
+    const int32_t lane = (int32_t)lane_id();
+    return wave_max(lane >= l0 && lane < l1 ? lm : 0u);
+}
+
+// ------------------------------------------------------------ tiles
+
+// A lane that a RAM window covers only in part: its bytes, the covered
+// byte range and its lane maximum.
+struct PartLane {
+    uint4 q;
+    int32_t a, b;
+    uint32_t ub, pad;
+};
+
+// Per-wave LDS staging: the bytes of G tiles and their lane maxima, and
+// room for a RAM window's partly covered lanes.
+template <int G>
+struct Ring {
+    uint4 t[G][kWave];
+    uint32_t lm[G][kWave];
+    PartLane park[2];
+};
+
+// A staged tile as a walker sees it: its position (relative to the segment
+// start) and its largest byte, both uniform; its bytes and lane maxima stay
+// in LDS and are read only where a chunk boundary falls into the tile.
+struct Tile {
+    const uint4* vp;
+    const uint32_t* lmp;
+    int32_t tp;
+    uint32_t tmax;
+    __device__ __forceinline__ uint4 v() const { return *vp; }
+    __device__ __forceinline__ uint32_t lm() const { return *lmp; }
+};
+
+// Largest byte M among positions [lo, hi) of the tile (lo < hi, both inside)
+// and, in *pos, the first position holding it.  The partly covered first
+// lane A is examined only when its lane maximum reaches the whole lanes'
+// maximum (it comes first, so a tie makes it the answer), the partly
+// covered last lane B only when its lane maximum exceeds everything before.
+__device__ __forceinline__ uint32_t tile_range_argmax(const Tile& t,
+                                                      const uint4& v,
+                                                      uint32_t lm, int32_t lo,
+                                                      int32_t hi, int32_t& pos) {
+    const int32_t tp = t.tp;
+    const int32_t lo_t = lo - tp, hi_t = hi - tp;
+    const int32_t fl = (lo_t + 15) >> 4, fh = hi_t >> 4;   // whole lanes [fl, fh)
+    int la = -1, lb = -1, aA = 0, bA = 16, bB = 16;
+    if (fl > fh) {                       // inside one lane
+        la = fh;
+        aA = lo_t & 15;
+        bA = hi_t & 15;
+    } else {
+        if (lo_t & 15) {
+            la = fl - 1;
+            aA = lo_t & 15;
+        }
+        if (hi_t & 15) {
+            lb = fh;
+            bB = hi_t & 15;
+        }
+    }
+    const uint32_t mF = (fl == 0 && fh == kWave) ? t.tmax : lanes_max(lm, fl, fh);
+    Lane16 qA{0, 0, 0, 0}, qB{0, 0, 0, 0};
+    uint32_t mA = 0, mB = 0;
+    bool hasA = false;
+    if (la >= 0 && (uint32_t)__builtin_amdgcn_readlane((int)lm, la) >= mF) {
+        qA = lane_words(v, la);
+        mA = lane_range_max(qA, aA, bA);
+        hasA = true;
+    }
+    const uint32_t M1 = max(mA, mF);
+    if (lb >= 0 && (uint32_t)__builtin_amdgcn_readlane((int)lm, lb) > M1) {
+        qB = lane_words(v, lb);
+        mB = lane_range_max(qB, 0, bB);
+    }
+    const uint32_t M = max(M1, mB);
+    if (hasA && mA == M) {
+        pos = tp + 16 * la + lane_first_ge(qA, aA, bA, M);
+    } else if (fl < fh && mF == M) {
+        const int32_t lane = (int32_t)lane_id();
+        const int f = __builtin_ctzll(__ballot(lane >= fl && lane < fh && lm == M));
+        pos = tp + 16 * f + lane_first_ge(lane_words(v, f), 0, 16, M);
+    } else {
+        pos = tp + 16 * lb + lane_first_ge(qB, 0, bB, M);
+    }
+    return M;
+}
+
 // ------------------------------------------------------------ walkers
 
-// Uniform state of one walker.  RAM: phase 0 accumulates the window maximum
-// in T, phase 1 scans for a byte >= T.  AE: p is the target and T the scan
-// threshold (target value + 1; 0 right after a cut).
-struct WState {
-    int32_t s, L, cur, p;
-    int32_t phase, T, pad0, pad1;
+// Uniform state of one walker.  RAM: the window is [s, we); T holds the
+// maximum so far, then the scan threshold (scan = 1).  AE: we is the target
+// position and T the threshold (target byte + 1), -1 at a chunk start (the
+// chunk's first byte is its first target), > 255 when nothing can exceed
+// the target.
+struct Walker {
+    int32_t s, L, cur, we, T, scan;
 };
 
 // n: job length relative to the segment start, clamped far beyond anything
 // a walker of this segment reaches.
-struct ChainCtx {
+struct Ctx {
     int32_t n, w, M;
 };
 
 constexpr int32_t kRelClamp = 0x7FFFF000;
 
-__device__ __forceinline__ ChainCtx chain_ctx(const JobView& J, int64_t a) {
-    ChainCtx C;
+__device__ __forceinline__ Ctx ctx_of(const JobView& J, int64_t a) {
+    Ctx C;
     C.n = (int32_t)min(J.n - a, (int64_t)kRelClamp);
     C.w = (int32_t)J.w;
     C.M = (int32_t)J.M;
     return C;
 }
 
-// Start a walker at chunk start s0.  Returns true if the chunk is already
-// decided without reading (RAM's last chunk when the window does not fit);
-// then *c_out is its end.
-template <bool RAM>
-__device__ __forceinline__ bool walker_start(WState& W, const ChainCtx& C,
-                                             int32_t s0, int32_t* c_out) {
-    W.s = s0;
-    W.L = min(C.n, s0 + C.M);
-    W.cur = s0;
-    W.p = s0 - 1;
-    W.phase = 0;
+// Start a RAM chunk at c.  When the window does not fit before the limit
+// (which then is n), the chunk's end is decided without reading: returns
+// true with *end = n.
+__device__ __forceinline__ bool ram_start(Walker& W, const Ctx& C, int32_t c,
+                                          int32_t* end) {
+    W.s = c;
+    W.L = min(C.n, c + C.M);
+    W.cur = c;
+    W.we = c + C.w;
     W.T = 0;
-    if (RAM && s0 + C.w >= W.L) {
-        *c_out = W.L;
+    W.scan = 0;
+    if (W.we >= W.L) {
+        *end = W.L;
         return true;
     }
     return false;
 }
 
-// Advance a walker over one tile.  emit(c) is called for every chunk end c
-// and returns true to stop the walker; returns true once stopped.
-template <bool RAM, class Emit>
-__device__ __forceinline__ bool walker_step(WState& W, const ChainCtx& C,
-                                            const uint4& v, uint32_t lm,
-                                            uint32_t tmax, int32_t tp,
-                                            Emit& emit) {
-    const int32_t te = tp + kTile;
-    if (W.cur >= te) return false;   // starts in a later tile
+__device__ __forceinline__ void ae_start(Walker& W, const Ctx& C, int32_t c) {
+    W.s = c;
+    W.L = min(C.n, c + C.M);
+    W.cur = c;
+    W.we = c;
+    W.T = -1;
+    W.scan = 0;
+}
+
+// Window maximum under construction (RAM): whole tiles go into the
+// walker's T; lanes wholly inside the window of its first and last tiles go
+// into acc (reduced once, where the window ends); the at most two lanes that
+// the window covers only in part are parked in LDS with their byte range and
+// their lane maximum, an upper bound of their part, and are reduced exactly
+// only when that bound exceeds the rest of the window.  Keeping them out of
+// registers keeps the per-tile loop's live state small.
+struct RamWin {
+    uint32_t acc;                        // per lane
+    int np;
+    PartLane* park;                      // two entries in LDS (per wave)
+
+    __device__ __forceinline__ void reset() {
+        acc = 0;
+        np = 0;
+    }
+    __device__ __forceinline__ void part(const uint4& v, uint32_t lm, int l,
+                                         int32_t a_, int32_t b_) {
+        const Lane16 w = lane_words(v, l);
+        const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)lm, l);
+        if (lane_id() == 0)
+            park[np] = PartLane{make_uint4(w.d0, w.d1, w.d2, w.d3), a_, b_, u, 0};
+        np++;
+    }
+    __device__ __forceinline__ uint32_t finish(uint32_t T) {
+        T = max(T, uni(wave_max(acc)));
+        for (int i = 0; i < np; i++) {
+            const PartLane p = park[i];
+            const uint32_t ub = uni(p.ub);
+            if (ub > T) {
+                const Lane16 q{uni(p.q.x), uni(p.q.y), uni(p.q.z), uni(p.q.w)};
+                T = max(T, lane_range_max(q, (int)uni((uint32_t)p.a), (int)uni((uint32_t)p.b)));
+            }
+        }
+        return T;
+    }
+};
+
+// Advance a RAM walker over a tile.  emit(c) is called for every chunk end
+// c and returns true to stop the walker; returns true once stopped.  A tile
+// that only continues a window, or that a scan crosses without a hit, costs
+// a few scalar compares on its maximum.
+template <class Emit>
+__device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
+                                         const Tile& t, Emit& emit) {
+    const int32_t tp = t.tp, te = tp + kTile;
+    if (W.cur >= te) return false;
+    if (W.cur == tp) {                   // continuing from the previous tile
+        if (!W.scan) {
+            if (W.we > te) {             // the whole tile is window
+                W.T = max(W.T, (int32_t)t.tmax);
+                W.cur = te;
+                return false;
+            }
+        } else if (W.L > te && (int32_t)t.tmax < W.T) {
+            W.cur = te;                  // no byte >= T, no limit here
+            return false;
+        }
+    }
+    const uint4 v = t.v();
+    const uint32_t lm = t.lm();
+    const int32_t lane = (int32_t)lane_id();
     for (;;) {
+        if (!W.scan) {
+            // window bytes [cur, min(we, te)) of this tile
+            const int32_t lo_t = W.cur - tp, hi_t = min(W.we, te) - tp;
+            const int32_t fl = (lo_t + 15) >> 4, fh = hi_t >> 4;
+            if (fl == 0 && fh == kWave) {
+                W.T = max(W.T, (int32_t)t.tmax);
+            } else if (fl > fh) {        // inside one lane
+                X.part(v, lm, fh, lo_t & 15, hi_t & 15);
+            } else {
+                if (fl < fh && lane >= fl && lane < fh) X.acc = max(X.acc, lm);
+                if (lo_t & 15) X.part(v, lm, fl - 1, lo_t & 15, 16);
+                if (hi_t & 15) X.part(v, lm, fh, 0, hi_t & 15);
+            }
+            if (W.we > te) {
+                W.cur = te;
+                return false;
+            }
+            W.T = (int32_t)X.finish((uint32_t)W.T);
+            X.reset();
+            W.scan = 1;
+            W.cur = W.we;
+        }
+        const int32_t hi = min(W.L, te);
+        int32_t j = -1;
+        if (W.cur < hi) {
+            if (W.T == 0) {
+                j = W.cur;               // every byte is >= 0
+            } else if ((int32_t)t.tmax >= W.T) {
+                uint32_t val;
+                j = tile_find_ge(v, lm, tp, W.cur, hi, (uint32_t)W.T, val);
+            }
+        }
         int32_t c;
-        if (RAM) {
-            if (W.phase == 0) {
-                const int32_t we = W.s + C.w;
-                const int32_t hi = min(we, te);
-                const uint32_t m = (W.cur <= tp && hi >= te)
-                                       ? tmax
-                                       : range_max(v, lm, tp, W.cur, hi);
-                W.T = max(W.T, (int32_t)m);
-                if (we > te) {
-                    W.cur = te;
-                    return false;
-                }
-                W.phase = 1;
-                W.cur = we;
-            }
-            const int32_t hi = min(W.L, te);
-            int32_t j = -1;
-            uint32_t val = 0;
-            if (!(W.cur <= tp && hi >= te && (int32_t)tmax < W.T))
-                j = find_first(v, lm, tp, W.cur, hi, W.T, val);
-            if (j >= 0)
-                c = j + 1;
-            else if (W.L <= te)
-                c = W.L;
-            else {
-                W.cur = te;
-                return false;
-            }
-        } else {
-            const int32_t wend = min(W.p + C.w + 1, W.L);
-            const int32_t hi = min(wend, te);
-            int32_t j = -1;
-            uint32_t val = 0;
-            if (!(W.cur <= tp && hi >= te && (int32_t)tmax < W.T))
-                j = find_first(v, lm, tp, W.cur, hi, W.T, val);
-            if (j >= 0) {
-                W.p = j;
-                W.T = (int32_t)val + 1;
-                W.cur = j + 1;
-                continue;
-            }
-            if (wend > te) {
-                W.cur = te;
-                return false;
-            }
-            c = wend;
+        if (j >= 0)
+            c = j + 1;
+        else if (W.L <= te)
+            c = W.L;
+        else {
+            W.cur = te;
+            return false;
         }
         if (emit(c)) return true;
-        int32_t last;
-        if (walker_start<RAM>(W, C, c, &last)) {
-            emit(last);          // last == n: every walker stops there
+        int32_t end;
+        if (ram_start(W, C, c, &end)) {
+            emit(end);                   // end == n: every walker stops there
             return true;
         }
         if (W.cur >= te) return false;
     }
 }
 
-// Per-wave LDS: the staging ring and the front walkers' states.
-template <int G>
-struct WaveLdsT {
-    uint4 ring[G][kWave];
-    WState front[kFront];
-};
-using WaveLds = WaveLdsT<kGroup>;
-using SoloLds = WaveLdsT<kGroupSolo>;
-
-// Streams tiles from the one holding first_pos: kGroup tiles are loaded into
-// registers while the previous kGroup are processed from the LDS ring.
-// body(v, lm, tmax, tp) returns true when the wave is done.  A hard stop
-// past the end of the job guarantees every wave exits.
-template <bool INV, int G, class Body>
-__device__ __forceinline__ void run_tiles(const Source& src, WaveLdsT<G>& L,
-                                          int64_t base, int32_t first_rel,
-                                          int64_t n, Body&& body,
-                                          uint32_t* err) {
-    int64_t t = src.tile_of(base + first_rel);
-    const int64_t t_end = src.tile_of(n) + 1;
-    uint4 c[G];
-#pragma unroll
-    for (int i = 0; i < G; i++) c[i] = src.load<INV>(t + i);
-#pragma unroll
-    for (int i = 0; i < G; i++) L.ring[i][lane_id()] = c[i];
+// Advance an AE walker over a tile (as ram_tile).
+template <class Emit>
+__device__ __forceinline__ bool ae_tile(Walker& W, const Ctx& C, const Tile& t,
+                                        Emit& emit) {
+    const int32_t tp = t.tp, te = tp + kTile;
+    if (W.cur >= te) return false;
+    if (W.cur == tp && W.T >= 0 && min(W.we + C.w + 1, W.L) > te &&
+        (int32_t)t.tmax < W.T) {
+        W.cur = te;                      // nothing in the tile exceeds the target
+        return false;
+    }
+    const uint4 v = t.v();
+    const uint32_t lm = t.lm();
     for (;;) {
-#pragma unroll
-        for (int i = 0; i < G; i++) c[i] = src.load<INV>(t + G + i);
-        for (int i = 0; i < G; i++) {
-            if (t + i > t_end) {
-                if (lane_id() == 0) atomicOr(err, kErrOverflow);
-                return;
-            }
-            const uint4 v = L.ring[i][lane_id()];
-            const uint32_t lm = lane_max16(v);
-            const uint32_t tmax = wave_max(lm);
-            if (body(v, lm, tmax, (int32_t)(src.tile_pos(t + i) - base)))
-                return;
+        if (W.T < 0) {                   // the chunk's first byte
+            const int32_t o = W.cur - tp;
+            const uint32_t dw = (uint32_t)__builtin_amdgcn_readlane(
+                (int)pick_dword(v, (o & 15) >> 2), o >> 4);
+            W.we = W.cur;
+            W.T = (int32_t)((dw >> (8 * (o & 3))) & 0xFFu) + 1;
+            W.cur++;
         }
-#pragma unroll
-        for (int i = 0; i < G; i++) L.ring[i][lane_id()] = c[i];
-        t += G;
+        const int32_t wend = min(W.we + C.w + 1, W.L);
+        const int32_t hi = min(wend, te);
+        if (W.T <= (int32_t)t.tmax && W.cur < hi) {
+            uint32_t val;
+            const int32_t j = tile_find_ge(v, lm, tp, W.cur, hi, (uint32_t)W.T, val);
+            if (j >= 0 && C.w >= kTile) {
+                // Every later record in this tile lies within the window of
+                // the one before it, so the target ends at the first
+                // maximum of [j, min(te, L)).
+                const int32_t hl = min(te, W.L);
+                int32_t q;
+                const uint32_t M = tile_range_argmax(t, v, lm, j, hl, q);
+                W.we = q;
+                W.T = (int32_t)M + 1;
+                W.cur = hl;
+                if (W.cur >= te) return false;
+                continue;
+            }
+            if (j >= 0) {                // a greater byte: the new target
+                W.we = j;
+                W.T = (int32_t)val + 1;
+                W.cur = j + 1;
+                if (W.cur >= te) return false;
+                continue;
+            }
+        }
+        if (wend > te) {
+            W.cur = te;
+            return false;
+        }
+        if (emit(wend)) return true;
+        ae_start(W, C, wend);
+        if (W.cur >= te) return false;
     }
 }
 
-// ------------------------------------------------------------ storage
-
-__device__ __forceinline__ uint32_t* main_list(const JobView& J,
-                                               const ChainWs& ws, uint32_t seg) {
-    return ws.spec + J.slot0 + (uint64_t)seg * J.cap;
-}
-__device__ __forceinline__ uint32_t* fix_list(const JobView& J,
-                                              const ChainWs& ws, uint32_t seg) {
-    return ws.fix + J.slot0 + (uint64_t)seg * J.cap;
-}
-__device__ __forceinline__ uint32_t* front_list(const ChainWs& ws,
-                                                uint32_t item, int f) {
-    return ws.front + ((uint64_t)item * kFront + f) * kFL;
+// One tile's 16-byte piece for this lane from granule pointer p; only lanes
+// below `valid` read (the others get zeros).
+template <bool INV>
+__device__ __forceinline__ uint4 ld_tile(const uint4* p, int32_t valid) {
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if ((int32_t)lane_id() < valid) {
+        const u32x4 q = __builtin_nontemporal_load((const global_u32x4*)p);
+        r = make_uint4(q.x, q.y, q.z, q.w);
+    }
+    if (INV) r = make_uint4(~r.x, ~r.y, ~r.z, ~r.w);
+    return r;
 }
 
-// Offsets of the front walkers' starts: kFront + 1 evenly spaced starts
-// (the main walker's included) over w + 512 bytes, the usual reach of a
-// chunk; only for windows of at least one tile, where a walker ends at most
-// one chunk per tile.
-__device__ __forceinline__ int front_count(const JobView& J, const ChainCtx& C,
-                                           int32_t b, int32_t& spacing) {
-    if (C.w < kTile || !J.front) return 0;
-    spacing = (C.w + 512) / (kFront + 1);
-    int nf = 0;
-    while (nf < kFront && (nf + 1) * spacing < b &&
-           (nf + 1) * spacing + C.w < C.n)
-        nf++;
-    return nf;
+__device__ __forceinline__ int32_t lanes_valid(int64_t rem) {
+    return (int32_t)min(max(rem, (int64_t)0), (int64_t)kWave);
+}
+
+// Stage a loaded group: the lane maxima and tile maxima of all G tiles are
+// computed together (independent chains, so the vector unit stays busy),
+// then the bytes and lane maxima go to LDS; the tile maxima are packed a
+// byte each into tmx.
+template <int G>
+__device__ __forceinline__ void stage(Ring<G>& R, const uint4 (&c)[G],
+                                      uint64_t (&tmx)[(G + 7) / 8]) {
+    uint32_t lm[G], tm[G];
+#pragma unroll
+    for (int i = 0; i < G; i++) lm[i] = lane_max16(c[i]);
+#pragma unroll
+    for (int i = 0; i < G; i++) tm[i] = wave_max(lm[i]);
+#pragma unroll
+    for (int i = 0; i < G; i++) {
+        R.t[i][lane_id()] = c[i];
+        R.lm[i][lane_id()] = lm[i];
+    }
+#pragma unroll
+    for (int k = 0; k < (G + 7) / 8; k++) {
+        uint64_t p = 0;
+#pragma unroll
+        for (int i = 0; i < 8 && 8 * k + i < G; i++) p |= (uint64_t)tm[8 * k + i] << (8 * i);
+        tmx[k] = p;
+    }
+}
+
+// Streams tiles from the one holding position first_rel (relative to base):
+// G tiles are loaded into registers while the previous G are processed from
+// the LDS ring.  body(tile) returns true when the wave is done.  A hard stop
+// one tile past the end of the job guarantees every wave exits.
+template <bool INV, int G, class Body>
+__device__ __forceinline__ void run_tiles(const Source& src, Ring<G>& R,
+                                          int64_t base, int32_t first_rel,
+                                          int64_t n, Body&& body,
+                                          uint32_t* err) {
+    const int64_t t0 = src.tile_of(base + first_rel);
+    int32_t left = (int32_t)min(src.tile_of(n) + 2 - t0, (int64_t)0x7FFFFFFF);
+    int32_t tp = (int32_t)(src.tile_pos(t0) - base);
+    const uint4* p = src.base + t0 * kWave + lane_id();
+    int64_t rem = (int64_t)src.ngran - t0 * kWave;   // granules from tile t0 on
+    uint4 c[G];
+    uint64_t tmx[(G + 7) / 8];
+#pragma unroll
+    for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
+    stage(R, c, tmx);
+    for (;;) {
+        p += kWave * G;
+        rem -= kWave * G;
+#pragma unroll
+        for (int i = 0; i < G; i++)
+            c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
+        for (int i = 0; i < G; i++) {
+            if (--left < 0) {
+                if (lane_id() == 0) atomicOr(err, kErrOverflow);
+                return;
+            }
+            Tile t;
+            t.vp = &R.t[i][lane_id()];
+            t.lmp = &R.lm[i][lane_id()];
+            t.tp = tp;
+            t.tmax = (uint32_t)(tmx[i >> 3] >> (8 * (i & 7))) & 0xFFu;
+            if (body(t)) return;
+            tp += kTile;
+        }
+        stage(R, c, tmx);
+    }
+}
+
+// Run one walker of the job from chunk start `start` (relative to base).
+template <bool RAM, bool INV, int G, class Emit>
+__device__ __forceinline__ void walk(const JobView& J, const Ctx& C,
+                                     Ring<G>& R, int64_t base, int32_t start,
+                                     Emit& emit, uint32_t* err) {
+    Walker W;
+    RamWin X;
+    X.park = R.park;
+    X.reset();
+    if (RAM) {
+        int32_t end;
+        if (ram_start(W, C, start, &end)) {
+            emit(end);
+            return;
+        }
+    } else {
+        ae_start(W, C, start);
+    }
+    Source src;
+    src.init(J.data, (uint64_t)J.n);
+    run_tiles<INV>(src, R, base, start, J.n,
+                   [&](const Tile& t) -> bool {
+                       if constexpr (RAM)
+                           return ram_tile(W, X, C, t, emit);
+                       else
+                           return ae_tile(W, C, t, emit);
+                   },
+                   err);
+}
+
+// ------------------------------------------------------------ lists
+
+// Writer of a cut list: positions collect in the lanes of one register and
+// go out 64 at a time.
+struct CutList {
+    uint32_t* dst;
+    uint32_t cap;
+    uint32_t n;
+    uint32_t buf;
+    uint32_t* err;
+
+    __device__ void init(uint32_t* d, uint32_t c, uint32_t* e) {
+        dst = d;
+        cap = c;
+        n = 0;
+        buf = 0;
+        err = e;
+    }
+    __device__ __forceinline__ void push(uint32_t c) {
+        const uint32_t k = n & 63u;
+        if (lane_id() == k) buf = c;
+        n++;
+        if (k == 63u) {
+            const uint32_t i = n - 64u + lane_id();
+            if (i < cap) dst[i] = buf;
+        }
+    }
+    __device__ void finish() {
+        const uint32_t k = n & 63u;
+        const uint32_t i = n - k + lane_id();
+        if (lane_id() < k && i < cap) dst[i] = buf;
+        if (n > cap && lane_id() == 0) atomicOr(err, kErrOverflow);
+    }
+};
+
+// Cursor over an increasing list in global memory, 64 entries per load, for
+// lookups of increasing positions.
+struct ListCursor {
+    const uint32_t* src;
+    uint32_t n, base, vals, last;
+
+    __device__ void load() {
+        const uint32_t i = base + lane_id();
+        vals = i < n ? src[i] : kNone;
+        last = (uint32_t)__builtin_amdgcn_readlane((int)vals, 63);
+    }
+    __device__ void init(const uint32_t* s, uint32_t cnt) {
+        src = s;
+        n = cnt;
+        base = 0;
+        load();
+    }
+    // Index of c in the list, or -1; successive calls pass increasing c.
+    __device__ __forceinline__ int32_t find(uint32_t c) {
+        while (c > last && base + 64u < n) {
+            base += 64u;
+            load();
+        }
+        const uint64_t hit = __ballot(vals == c);
+        return hit ? (int32_t)(base + (uint32_t)__builtin_ctzll(hit)) : -1;
+    }
+};
+
+__device__ __forceinline__ uint32_t* list_of(const JobView& J,
+                                             const ChainWs& ws, uint32_t seg,
+                                             uint32_t list) {
+    uint32_t* b = list == kListSpec ? ws.spec : list == kListFix ? ws.fix : ws.rew;
+    return b + J.slot0 + (uint64_t)seg * J.cap;
 }
 
 // ------------------------------------------------------------ speculate
 
 template <bool RAM, bool INV>
 __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
-                          const ChainWs& ws, WaveLds& L) {
+                          const ChainWs& ws, Ring<kGroup>& R) {
     const int64_t a = (int64_t)seg * J.seg;
-    const ChainCtx C = chain_ctx(J, a);
+    const Ctx C = ctx_of(J, a);
     const int32_t b = (int32_t)(min(J.n, a + J.seg) - a);
-    uint32_t* mlist = main_list(J, ws, seg);
-    const uint32_t cap = J.cap;
-    uint32_t ncut = 0;
-    int32_t mlast = 0;
-    bool main_alive = true;
-
-    auto emit_main = [&](int32_t c) -> bool {
-        if (ncut < cap) {
-            if (lane_id() == 0) mlist[ncut] = (uint32_t)c;
-        } else if (lane_id() == 0) {
-            atomicOr(ws.err, kErrOverflow);
-        }
-        ncut++;
-        mlast = c;
+    CutList out;
+    out.init(list_of(J, ws, seg, kListSpec), J.cap, ws.err);
+    int32_t last = 0;
+    auto emit = [&](int32_t c) -> bool {
+        out.push((uint32_t)c);
+        last = c;
         return c >= b;
     };
-
-    WState W0;
-    int32_t c0;
-    if (walker_start<RAM>(W0, C, 0, &c0)) {
-        emit_main(c0);
-        main_alive = false;
-    }
-
-    // front walkers: states in LDS, stored-position counts in fcnt
-    int32_t spacing = 0;
-    const int nf = front_count(J, C, b, spacing);
-    FrontMeta* fm = ws.fmeta + (uint64_t)item * kFront;
-    uint32_t alive = 0;
-    uint32_t fcnt[kFront];
-#pragma unroll
-    for (int f = 0; f < kFront; f++) fcnt[f] = 1;
-    for (int f = 0; f < nf; f++) {
-        const int32_t s0 = (f + 1) * spacing;
-        WState W;
-        int32_t cd;
-        walker_start<RAM>(W, C, s0, &cd);   // s0 + w < n: the window fits
-        if (lane_id() == 0) {
-            L.front[f] = W;
-            front_list(ws, item, f)[0] = (uint32_t)s0;
-        }
-        alive |= 1u << f;
-    }
-
-    auto body = [&](const uint4& v, uint32_t lm, uint32_t tmax,
-                    int32_t tp) -> bool {
-        if (main_alive &&
-            walker_step<RAM>(W0, C, v, lm, tmax, tp, emit_main))
-            main_alive = false;
-        uint32_t todo = alive;
-        while (todo) {
-            const int f = __builtin_ctz(todo);
-            todo &= todo - 1;
-            WState W = L.front[f];
-            W.s = (int32_t)uni((uint32_t)W.s);
-            W.L = (int32_t)uni((uint32_t)W.L);
-            W.cur = (int32_t)uni((uint32_t)W.cur);
-            W.p = (int32_t)uni((uint32_t)W.p);
-            W.phase = (int32_t)uni((uint32_t)W.phase);
-            W.T = (int32_t)uni((uint32_t)W.T);
-            if (W.cur >= tp + kTile) continue;   // starts in a later tile
-            uint32_t* flist = front_list(ws, item, f);
-            uint32_t cnt = fcnt[0];
-#pragma unroll
-            for (int q = 1; q < kFront; q++)
-                if (q == f) cnt = fcnt[q];
-            auto emit_front = [&](int32_t c) -> bool {
-                // coalescence with the main walker or a lower front walker:
-                // equal cuts are reached in the same tile
-                uint32_t into = 0xFFFFFFFFu;
-                if (main_alive ? c == W0.s : c == mlast)
-                    into = 0;
-                else {
-                    const uint32_t l = lane_id();
-                    const bool m = l < (uint32_t)f && ((alive >> l) & 1u) &&
-                                   L.front[l < kFront ? l : 0].s == c;
-                    const uint64_t bb = __ballot(m);
-                    if (bb) into = (uint32_t)__builtin_ctzll(bb) + 1;
-                }
-                if (into != 0xFFFFFFFFu) {
-                    if (lane_id() == 0) fm[f] = FrontMeta{cnt, into, (uint32_t)c, 0};
-                    return true;
-                }
-                if (lane_id() == 0) flist[cnt] = (uint32_t)c;
-                cnt++;
-                if (c >= b) {
-                    if (lane_id() == 0) fm[f] = FrontMeta{cnt, kEndExit, (uint32_t)c, 0};
-                    return true;
-                }
-                if (cnt == (uint32_t)kFL) {
-                    if (lane_id() == 0) fm[f] = FrontMeta{cnt, kEndTrunc, (uint32_t)c, 0};
-                    return true;
-                }
-                return false;
-            };
-            if (walker_step<RAM>(W, C, v, lm, tmax, tp, emit_front))
-                alive &= ~(1u << f);
-#pragma unroll
-            for (int q = 0; q < kFront; q++)
-                if (q == f) fcnt[q] = cnt;
-            if (lane_id() == 0) L.front[f] = W;
-        }
-        return !main_alive && alive == 0;
-    };
-    if (main_alive || alive) {
-        Source src;
-        src.init(J.data, (uint64_t)J.n);
-        run_tiles<INV>(src, L, a, 0, J.n, body, ws.err);
-    }
+    walk<RAM, INV>(J, C, R, a, 0, emit, ws.err);
+    out.finish();
     if (lane_id() == 0) {
         SegMeta& m = ws.meta[item];
-        m.exit = (uint64_t)(a + mlast);
-        m.nspec = min(ncut, cap);
-        m.nfront = (uint32_t)nf;
+        m.exit = (uint64_t)(a + last);
+        m.nspec = min(out.n, J.cap);
     }
 }
 
 // ------------------------------------------------------------ resolve
 
-// Membership of positions in the walkers' stored lists of one segment
-// (positions relative to the segment start).
-struct Lists {
-    const uint32_t* main;
-    uint32_t nspec;
-    uint32_t fval[kFront];   // lane l: entry l of front list f (or ~0)
-    uint32_t fcnt[kFront];
-    uint32_t fend[kFront];
-    uint32_t fdpos[kFront];
-    int nf;
-
-    // Index of r in the main list (scanning 64 entries at a time), or -1.
-    __device__ int32_t find_main(uint32_t r) const {
-        for (uint32_t base = 0; base < nspec; base += kWave) {
-            const uint32_t i = base + lane_id();
-            const uint32_t x = i < nspec ? main[i] : 0xFFFFFFFFu;
-            const uint64_t hit = __ballot(x == r);
-            if (hit) return (int32_t)(base + __builtin_ctzll(hit));
-            const uint32_t lastv = __builtin_amdgcn_readlane(
-                x, (int)min(nspec - 1 - base, 63u));
-            if (lastv > r) return -1;
+// Resolve segment `seg` from entry X (absolute, >= the segment start): the
+// chain from X is followed until a cut lands on the speculative list (or,
+// after the fix-up round, on the fix-up list, whose continuation is known);
+// the cuts before that are written to the fix-up list (fix-up round) or the
+// re-walk list.  Records the resolution (entry, pieces, count, exit) and
+// returns its exit.
+template <bool RAM, bool INV>
+__device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
+                                int64_t X, bool fixup, const ChainWs& ws,
+                                Ring<kGroupSolo>& R) {
+    const int64_t a = (int64_t)seg * J.seg;
+    const Ctx C = ctx_of(J, a);
+    const int32_t b = (int32_t)(min(J.n, a + J.seg) - a);
+    SegMeta& m = ws.meta[item];
+    const uint32_t nspec = uni(m.nspec);
+    const int64_t sexit = uni64((int64_t)m.exit);
+    uint32_t nfix = 0, fms = kNone;
+    int64_t fexit = 0, fentry = -1;
+    if (!fixup) {
+        nfix = uni(m.nfix);
+        fms = uni(m.fms);
+        fexit = uni64((int64_t)m.fexit);
+        fentry = seg == 0 ? a : uni64((int64_t)ws.meta[item - 1].exit);
+    }
+    const uint32_t own = fixup ? kListFix : kListRewalk;
+    uint32_t np = 0, count = 0;
+    int64_t rexit = X;
+    auto add = [&](uint32_t list, uint32_t lo, uint32_t hi) {
+        hi = min(hi, J.cap);             // a list never holds more (else flagged)
+        if (hi > lo) {
+            if (lane_id() == 0) m.pieces[np] = Piece{list, lo, hi};
+            np++;
+            count += hi - lo;
         }
-        return -1;
+    };
+    // the fix-up chain from its index i on
+    auto follow_fix = [&](uint32_t i) {
+        add(kListFix, i, nfix);
+        if (fms != kNone) {
+            add(kListSpec, fms, nspec);
+            rexit = sexit;
+        } else {
+            rexit = fexit;
+        }
+    };
+    const int32_t e = (int32_t)(X - a);
+    // the fix-up chain's own record (fix-up round)
+    uint32_t new_nfix = 0, new_fms = kNone;
+    int64_t new_fexit = X;
+    bool settled = false;
+    if (e >= b) {
+        settled = true;                  // the chain jumps over the segment
+    } else if (e == 0) {
+        add(kListSpec, 0, nspec);
+        rexit = sexit;
+        new_fms = 0;
+        settled = true;
+    } else {
+        ListCursor cs;
+        cs.init(list_of(J, ws, seg, kListSpec), nspec);
+        const int32_t i = cs.find((uint32_t)e);
+        if (i >= 0) {
+            add(kListSpec, (uint32_t)i + 1, nspec);
+            rexit = sexit;
+            new_fms = (uint32_t)i + 1;
+            settled = true;
+        } else if (!fixup) {
+            if (X == fentry) {
+                follow_fix(0);
+                settled = true;
+            } else {
+                ListCursor cf;
+                cf.init(list_of(J, ws, seg, kListFix), nfix);
+                const int32_t f = cf.find((uint32_t)e);
+                if (f >= 0) {
+                    follow_fix((uint32_t)f + 1);
+                    settled = true;
+                }
+            }
+        }
     }
-    __device__ int32_t find_front(int f, uint32_t r) const {
-        uint32_t x = fval[0];
-#pragma unroll
-        for (int q = 1; q < kFront; q++)
-            if (q == f) x = fval[q];
-        const uint64_t hit = __ballot(x == r);
-        return hit ? (int32_t)__builtin_ctzll(hit) : -1;
-    }
-    // Walker list holding r: 0 main, f+1 front f.
-    __device__ bool find(uint32_t r, uint32_t& list, uint32_t& idx) const {
-#pragma unroll
-        for (int f = 0; f < kFront; f++) {
-            if (f >= nf) break;
-            const uint64_t hit = __ballot(fval[f] == r);
-            if (hit) {
-                list = f + 1;
-                idx = (uint32_t)__builtin_ctzll(hit);
+    if (!settled) {
+        CutList wl;
+        wl.init(list_of(J, ws, seg, own), J.cap, ws.err);
+        ListCursor cs, cf;
+        cs.init(list_of(J, ws, seg, kListSpec), nspec);
+        if (!fixup) cf.init(list_of(J, ws, seg, kListFix), nfix);
+        auto emit = [&](int32_t c) -> bool {
+            const int32_t i = cs.find((uint32_t)c);
+            if (i >= 0) {                // landed on the speculative chain
+                add(own, 0, wl.n);
+                add(kListSpec, (uint32_t)i, nspec);
+                rexit = sexit;
+                new_fms = (uint32_t)i;
                 return true;
             }
-        }
-        const int32_t m = find_main(r);
-        if (m >= 0) {
-            list = 0;
-            idx = (uint32_t)m;
-            return true;
-        }
-        return false;
-    }
-};
-
-struct FixOutcome {
-    int64_t exit;   // where the resolved chain leaves the segment (absolute)
-};
-
-// Resolve segment `seg` from the true-or-assumed entry `entry` (absolute,
-// >= segment start): fix-up cuts until the chain meets a recorded walker,
-// then the pieces of walker lists it follows.  Writes the segment's record.
-template <bool RAM, bool INV>
-__device__ FixOutcome resolve_segment(const JobView& J, uint32_t seg,
-                                      uint32_t item, int64_t entry,
-                                      const ChainWs& ws, SoloLds& L) {
-    const int64_t a = (int64_t)seg * J.seg;
-    const ChainCtx C = chain_ctx(J, a);
-    const int32_t b = (int32_t)(min(J.n, a + J.seg) - a);
-    const int32_t e = (int32_t)(entry - a);
-    SegMeta& m = ws.meta[item];
-    Lists Ls;
-    Ls.main = main_list(J, ws, seg);
-    Ls.nspec = uni(m.nspec);
-    Ls.nf = (int)uni(m.nfront);
-    const FrontMeta* fm = ws.fmeta + (uint64_t)item * kFront;
-#pragma unroll
-    for (int f = 0; f < kFront; f++) {
-        Ls.fcnt[f] = 0;
-        Ls.fend[f] = 0;
-        Ls.fdpos[f] = 0;
-        Ls.fval[f] = 0xFFFFFFFFu;
-        if (f < Ls.nf) {
-            Ls.fcnt[f] = uni(fm[f].count);
-            Ls.fend[f] = uni(fm[f].end);
-            Ls.fdpos[f] = uni(fm[f].dpos);
-            const uint32_t* fl = front_list(ws, item, f);
-            if (lane_id() < Ls.fcnt[f]) Ls.fval[f] = fl[lane_id()];
-        }
-    }
-    const int64_t main_exit = uni64((int64_t)m.exit);
-    uint32_t* fx = fix_list(J, ws, seg);
-    const uint32_t cap = J.cap;
-    uint32_t nfix = 0;
-    Piece pc[kMaxPieces];
-    uint32_t np = 0;
-    int64_t exit = entry;
-    uint32_t merged = 0;
-
-    auto put_fix = [&](uint32_t c) {
-        if (nfix < cap) {
-            if (lane_id() == 0) fx[nfix] = c;
-        } else if (lane_id() == 0) {
-            atomicOr(ws.err, kErrOverflow);
-        }
-        nfix++;
-    };
-
-    // where the chain is: on a walker list from index lo, or walking from a
-    // position
-    uint32_t list = 0, lo = 0;
-    bool on_list = false;
-    int32_t walk_from = -1;
-    uint32_t li, ix;
-    if (e == 0) {
-        on_list = true;
-    } else if (e < b && Ls.find((uint32_t)e, li, ix)) {
-        on_list = true;
-        list = li;
-        lo = ix + 1;
-    } else if (e < b) {
-        walk_from = e;
-    }
-
-    for (int round = 0; round < 64; round++) {
-        if (walk_from >= 0) {
-            // walk until a cut lands on a recorded walker or leaves
-            bool met = false;
-            auto emit_fix = [&](int32_t c) -> bool {
-                uint32_t l2, i2;
-                if (Ls.find((uint32_t)c, l2, i2)) {
-                    met = true;
-                    list = l2;
-                    lo = i2;
+            if (!fixup) {
+                const int32_t f = cf.find((uint32_t)c);
+                if (f >= 0) {            // landed on the fix-up chain
+                    add(own, 0, wl.n);
+                    follow_fix((uint32_t)f);
                     return true;
                 }
-                put_fix((uint32_t)c);
-                if (c >= b) {
-                    exit = a + c;
-                    return true;
-                }
-                return false;
-            };
-            WState W;
-            int32_t c0;
-            if (walker_start<RAM>(W, C, walk_from, &c0)) {
-                emit_fix(c0);
-            } else {
-                Source src;
-                src.init(J.data, (uint64_t)J.n);
-                auto body = [&](const uint4& v, uint32_t lm, uint32_t tmax,
-                                int32_t tp) -> bool {
-                    return walker_step<RAM>(W, C, v, lm, tmax, tp, emit_fix);
-                };
-                run_tiles<INV>(src, L, a, walk_from, J.n, body, ws.err);
             }
-            walk_from = -1;
-            if (!met) break;      // left the segment on its own
-            on_list = true;
-        }
-        if (!on_list) break;
-        // follow walker lists from (list, lo)
-        merged = 1;
-        bool resume = false;
-        for (int hop = 0; hop <= kFront; hop++) {
-            if (list == 0) {
-                pc[np++] = Piece{0, lo, Ls.nspec, 0};
-                exit = main_exit;
-                break;
+            wl.push((uint32_t)c);
+            if (c >= b) {                // left the segment on its own
+                add(own, 0, wl.n);
+                rexit = a + c;
+                new_fexit = rexit;
+                return true;
             }
-            const int f = (int)list - 1;
-            uint32_t fc = Ls.fcnt[0], fe = Ls.fend[0], fd = Ls.fdpos[0];
-#pragma unroll
-            for (int q = 1; q < kFront; q++)
-                if (q == f) {
-                    fc = Ls.fcnt[q];
-                    fe = Ls.fend[q];
-                    fd = Ls.fdpos[q];
-                }
-            pc[np++] = Piece{list, lo, fc, 0};
-            if (fe == kEndExit) {
-                exit = a + (int64_t)fd;
-                break;
-            }
-            if (fe == kEndTrunc) {
-                // the walker was cut off: copy the pieces into the fix-up
-                // list and continue walking from its last position
-                for (uint32_t q = 0; q < np; q++) {
-                    const uint32_t* src_list =
-                        pc[q].list == 0 ? Ls.main
-                                        : front_list(ws, item, (int)pc[q].list - 1);
-                    for (uint32_t i = pc[q].lo; i < pc[q].hi; i++)
-                        put_fix(src_list[i]);
-                }
-                np = 0;
-                walk_from = (int32_t)fd;
-                resume = true;
-                break;
-            }
-            // coalesced into walker fe at position fd
-            const int32_t idx =
-                fe == 0 ? Ls.find_main(fd) : Ls.find_front((int)fe - 1, fd);
-            if (idx < 0) {          // cannot happen: both lists hold fd
-                if (lane_id() == 0) atomicOr(ws.err, kErrOverflow);
-                exit = a + (int64_t)fd;
-                break;
-            }
-            list = fe;
-            lo = (uint32_t)idx;
-        }
-        if (!resume) break;
-        on_list = false;
+            return false;
+        };
+        walk<RAM, INV>(J, C, R, a, e, emit, ws.err);
+        wl.finish();
+        new_nfix = min(wl.n, J.cap);
     }
-    uint32_t count = min(nfix, cap);
-    for (uint32_t q = 0; q < np; q++) count += pc[q].hi - pc[q].lo;
     if (lane_id() == 0) {
-        m.nfix = min(nfix, cap);
-        m.count = count;
-        m.merged = merged;
+        if (fixup) {
+            m.nfix = new_nfix;
+            m.fms = new_fms;
+            m.fexit = (uint64_t)new_fexit;
+        }
         m.npieces = np;
-        for (uint32_t q = 0; q < np; q++) m.pieces[q] = pc[q];
-        m.h = (uint64_t)exit;
+        m.count = count;
+        m.entry = (uint64_t)X;
+        m.rexit = (uint64_t)rexit;
     }
-    return FixOutcome{exit};
+    return rexit;
 }
 
 // ------------------------------------------------------------ kernels
@@ -654,7 +800,7 @@ __device__ FixOutcome resolve_segment(const JobView& J, uint32_t seg,
 // Per-item kernels walk the items grid-stride, one wave per item.
 template <bool RAM, bool INV>
 __global__ __launch_bounds__(256) void k_spec(Plan P, ChainWs ws) {
-    __shared__ WaveLds lds[4];
+    __shared__ Ring<kGroup> lds[4];
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const uint32_t count = item_count(P);
     for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
@@ -665,19 +811,43 @@ __global__ __launch_bounds__(256) void k_spec(Plan P, ChainWs ws) {
     }
 }
 
+// Fix-up round: every segment from the previous segment's speculative exit
+// (segment 0 from the job start).
 template <bool RAM, bool INV>
 __global__ __launch_bounds__(64) void k_fix(Plan P, ChainWs ws) {
-    __shared__ SoloLds lds[1];
+    __shared__ Ring<kGroupSolo> lds[1];
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const uint32_t count = item_count(P);
     for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
         JobView J;
         uint32_t seg;
         if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
-        // segment 0 starts the chain; others assume the previous main exit
-        const int64_t entry =
-            seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
-        resolve_segment<RAM, INV>(J, seg, wid, entry, ws, lds[0]);
+        const int64_t X = seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
+        const int64_t h = resolve_from<RAM, INV>(J, seg, wid, X, true, ws, lds[0]);
+        if (lane_id() == 0) ws.meta[wid].xo[1] = (uint64_t)h;
+    }
+}
+
+// Parallel round r >= 2: a segment whose predecessor's exit (as of round
+// r-1) differs from the entry it was resolved from is resolved again.
+template <bool RAM, bool INV>
+__global__ __launch_bounds__(64) void k_round(Plan P, ChainWs ws, int r) {
+    __shared__ Ring<kGroupSolo> lds[1];
+    const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
+    const uint32_t count = item_count(P);
+    const int src = (r - 1) & 1, dst = r & 1;
+    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+        JobView J;
+        uint32_t seg;
+        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
+        SegMeta& m = ws.meta[wid];
+        int64_t h = uni64((int64_t)m.rexit);
+        if (seg > 0) {
+            const int64_t X = uni64((int64_t)ws.meta[wid - 1].xo[src]);
+            if (X != uni64((int64_t)m.entry))
+                h = resolve_from<RAM, INV>(J, seg, wid, X, false, ws, lds[0]);
+        }
+        if (lane_id() == 0) m.xo[dst] = (uint64_t)h;
     }
 }
 
@@ -698,69 +868,66 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
     return ex;
 }
 
-// Resolve one RAM / AE job with the whole block: segments whose true entry
-// is not the previous main exit are re-run in order by wave 0; then output
-// offsets are assigned.
+// Settle one RAM / AE job with the whole block: segments whose entry is not
+// their predecessor's resolved exit are resolved again, in order, by wave 0
+// (after the parallel rounds there are rarely any); then output offsets are
+// assigned.
 template <bool RAM, bool INV>
-__device__ void resolve_job(const JobView& J, const ChainWs& ws, SoloLds& lds0,
-                            uint64_t* sh, uint32_t* nm_list,
-                            uint32_t& nm_count, int64_t& carry_x) {
+__device__ void settle_job(const JobView& J, const ChainWs& ws,
+                           Ring<kGroupSolo>& lds0, uint64_t* sh,
+                           uint32_t* flagged, uint32_t& n_flagged) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
     SegMeta* M0 = ws.meta + J.item0;
-    const bool leader = tid < kWave;
-
-    // A segment whose resolved exit differs from its main exit hands its
-    // successor an entry the fix-up did not assume.
-    if (tid == 0) carry_x = -1;   // -1: the window's first entry is on track
-    __syncthreads();
-    for (uint32_t base = 0; base < J.nseg; base += nt) {
-        if (tid == 0) nm_count = 0;
+    for (uint32_t base = 1; base < J.nseg; base += nt) {
+        if (tid == 0) n_flagged = 0;
         __syncthreads();
         const uint32_t k = base + tid;
-        if (k + 1 < J.nseg && M0[k].h != M0[k].exit) {
-            const uint32_t slot = atomicAdd(&nm_count, 1u);
-            nm_list[slot] = k;
+        if (k < J.nseg && M0[k].entry != M0[k - 1].rexit) {
+            const uint32_t slot = atomicAdd(&n_flagged, 1u);
+            flagged[slot] = k;
         }
         __syncthreads();
-        const uint32_t cnt = nm_count;
-        if (cnt > 0 || carry_x >= 0) {
-            if (tid == 0) {
+        const uint32_t cnt = n_flagged;
+        if (cnt > 0) {
+            if (tid == 0) {              // in segment order
                 for (uint32_t i = 1; i < cnt; i++) {
-                    uint32_t v = nm_list[i], j = i;
-                    while (j > 0 && nm_list[j - 1] > v) {
-                        nm_list[j] = nm_list[j - 1];
+                    const uint32_t v = flagged[i];
+                    uint32_t j = i;
+                    while (j > 0 && flagged[j - 1] > v) {
+                        flagged[j] = flagged[j - 1];
                         j--;
                     }
-                    nm_list[j] = v;
+                    flagged[j] = v;
                 }
             }
             __syncthreads();
-            if (leader) {
-                int64_t x = uni64(carry_x);
-                uint32_t k2 = base;
+            if (tid < kWave) {
+                // Walk the flagged segments in order; a segment resolved
+                // again can change its successor's entry (also past this
+                // block's range), which is then resolved right away.
                 uint32_t li = 0;
-                const uint32_t end = min(base + nt, J.nseg);
-                while (k2 < end) {
-                    if (x < 0) {
-                        while (li < cnt && nm_list[li] < k2) li++;
-                        if (li == cnt) break;
-                        const uint32_t j = uni(nm_list[li]);
-                        x = uni64((int64_t)M0[j].h);
-                        k2 = j + 1;
+                uint32_t k2 = uni(flagged[0]);
+                int64_t prev = uni64((int64_t)M0[k2 - 1].rexit);
+                for (;;) {
+                    int64_t h = uni64((int64_t)M0[k2].rexit);
+                    if (prev != uni64((int64_t)M0[k2].entry))
+                        h = resolve_from<RAM, INV>(J, k2, J.item0 + k2, prev,
+                                                   false, ws, lds0);
+                    while (li < cnt && uni(flagged[li]) <= k2) li++;
+                    const uint32_t nxt = k2 + 1;
+                    if (nxt < J.nseg && uni64((int64_t)M0[nxt].entry) != h) {
+                        k2 = nxt;
+                        prev = h;
                         continue;
                     }
-                    const FixOutcome o = resolve_segment<RAM, INV>(
-                        J, k2, J.item0 + k2, x, ws, lds0);
-                    const int64_t mexit = uni64((int64_t)M0[k2].exit);
-                    x = (o.exit == mexit) ? -1 : o.exit;
-                    k2++;
+                    if (li == cnt) break;
+                    k2 = uni(flagged[li]);
+                    prev = uni64((int64_t)M0[k2 - 1].rexit);
                 }
-                if (lane_id() == 0) carry_x = (k2 >= end) ? x : -1;
             }
             __syncthreads();
         }
     }
-
     uint64_t carry = 0;
     for (uint32_t base = 0; base < J.nseg; base += nt) {
         const uint32_t k = base + tid;
@@ -773,28 +940,26 @@ __device__ void resolve_job(const JobView& J, const ChainWs& ws, SoloLds& lds0,
     if (tid == 0) *J.n_cuts = carry;
 }
 
-// Resolve RAM / AE jobs, one block per job (grid-stride over jobs).
+// Settle RAM / AE jobs, one block per job (grid-stride over jobs).
 template <bool RAM, bool INV>
 __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
                                                  const uint32_t* n_jobs_d,
                                                  ChainWs ws) {
-    __shared__ SoloLds lds[1];
+    __shared__ Ring<kGroupSolo> lds[1];
     __shared__ uint64_t sh[256];
-    __shared__ uint32_t nm_list[256];
-    __shared__ uint32_t nm_count;
-    __shared__ int64_t carry_x;
+    __shared__ uint32_t flagged[256];
+    __shared__ uint32_t n_flagged;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
-        JobView J = view(P.jobs ? P.jobs[job] : P.one);
+        const JobView J = view(P.jobs ? P.jobs[job] : P.one);
         const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
         if (J.ok && J.algo == want && J.n > 0)
-            resolve_job<RAM, INV>(J, ws, lds[0], sh, nm_list, nm_count, carry_x);
+            settle_job<RAM, INV>(J, ws, lds[0], sh, flagged, n_flagged);
         __syncthreads();
     }
 }
 
-
-// Copy one segment's resolved cuts: its fix-up cuts, then its pieces.
+// Copy one segment's resolved pieces to the output.
 __device__ void emit_segment(const JobView& J, uint32_t seg, uint32_t wid,
                              const ChainWs& ws) {
     const SegMeta& m = ws.meta[wid];
@@ -806,16 +971,11 @@ __device__ void emit_segment(const JobView& J, uint32_t seg, uint32_t wid,
         return;
     }
     uint64_t* out = J.cuts + o;
-    const uint32_t nfix = uni(m.nfix);
-    const uint32_t* fx = fix_list(J, ws, seg);
-    for (uint32_t i = lane_id(); i < nfix; i += kWave) out[i] = a + fx[i];
-    out += nfix;
     const uint32_t np = uni(m.npieces);
     for (uint32_t q = 0; q < np; q++) {
         const uint32_t list = uni(m.pieces[q].list);
         const uint32_t lo = uni(m.pieces[q].lo), hi = uni(m.pieces[q].hi);
-        const uint32_t* src = list == 0 ? main_list(J, ws, seg)
-                                        : front_list(ws, wid, (int)list - 1);
+        const uint32_t* src = list_of(J, ws, seg, list);
         for (uint32_t i = lo + lane_id(); i < hi; i += kWave)
             out[i - lo] = a + src[i];
         out += hi - lo;
@@ -850,6 +1010,9 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
     CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV>), grid, blk, 0, st, P, ws);
     CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV>), dim3(items_upper),
                dim3(kWave), 0, st, P, ws);
+    for (int r = 2; r < 2 + kRounds; r++)
+        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV>), dim3(items_upper),
+                   dim3(kWave), 0, st, P, ws, r);
     CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
                dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
                n_jobs_d, ws);

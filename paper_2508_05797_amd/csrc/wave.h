@@ -166,7 +166,7 @@ struct Source {
 struct JobView {
     const uint8_t* data;
     int64_t n, w, M, seg;
-    uint32_t algo, nseg, item0, cap, ok, blog, front;
+    uint32_t algo, nseg, item0, cap, ok, blog;
     uint64_t slot0, blk0;
     uint64_t* cuts;
     uint64_t* n_cuts;
@@ -185,7 +185,6 @@ __device__ __forceinline__ JobView view(const JobDesc& J) {
     v.cap = uni(J.cap);
     v.ok = uni((uint32_t)J.ok);
     v.blog = uni(J.blog);
-    v.front = uni(J.front);
     v.slot0 = (uint64_t)uni64((int64_t)J.slot0);
     v.blk0 = (uint64_t)uni64((int64_t)J.blk0);
     v.cuts = (uint64_t*)uni64((int64_t)J.cuts);

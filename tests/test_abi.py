@@ -60,12 +60,13 @@ def test_host_only_entry_points():
     assert L.cdc_set_tuning(ctypes.byref(T(8, 0, 0, 0))) == -1
     assert L.cdc_set_tuning(ctypes.byref(T(0, (1 << 28) + 1, 0, 0))) == -1
     assert L.cdc_set_tuning(ctypes.byref(T(0, 0, 9, 0))) == -1
+    assert L.cdc_set_tuning(ctypes.byref(T(0, 0, 0, 1))) == -1
     assert L.cdc_set_tuning(ctypes.byref(T(4096, 1 << 16, 2, 0))) == 0
     assert binding.get_tuning() == {"chain_segment": 4096, "maxp_segment": 65536,
-                                    "waves_per_block": 2, "front_walkers": 0}
+                                    "waves_per_block": 2, "reserved": 0}
     assert L.cdc_set_tuning(None) == 0
     assert binding.get_tuning() == {"chain_segment": 1 << 20, "maxp_segment": 1 << 16,
-                                    "waves_per_block": 4, "front_walkers": 0}
+                                    "waves_per_block": 4, "reserved": 0}
     assert L.cdc_autotune(None, 1, None, 1, None) == -1
     assert L.cdc_get_tuning(None) == -1
     # the serving loop validates before creating streams
