@@ -143,8 +143,7 @@ __device__ __forceinline__ uint32_t lanes_max(uint32_t lm, int32_t l0,
 
 // ------------------------------------------------------------ tiles
 
-// A lane that a RAM window covers only in part: its bytes, the covered
-// byte range and its lane maximum.
+// One lane's bytes and lane maximum, parked for a RAM window.
 struct PartLane {
     uint4 q;
     int32_t a, b;
@@ -155,9 +154,10 @@ struct PartLane {
 // room for a RAM window's partly covered lanes.
 template <int G>
 struct Ring {
+    static constexpr bool kCoop = false;
     uint4 t[G][kWave];
     uint32_t lm[G][kWave];
-    PartLane park[2];
+    PartLane park[2 * kWave];
 };
 
 // A staged tile as a walker sees it: its position (relative to the segment
@@ -282,38 +282,51 @@ __device__ __forceinline__ void ae_start(Walker& W, const Ctx& C, int32_t c) {
 
 // Window maximum under construction (RAM): whole tiles go into the
 // walker's T; lanes wholly inside the window of its first and last tiles go
-// into acc (reduced once, where the window ends); the at most two lanes that
-// the window covers only in part are parked in LDS with their byte range and
-// their lane maximum, an upper bound of their part, and are reduced exactly
-// only when that bound exceeds the rest of the window.  Keeping them out of
-// registers keeps the per-tile loop's live state small.
+// into acc (reduced once, where the window ends); for the at most two lanes
+// that the window covers only in part, every lane parks its bytes and lane
+// maximum in LDS (a plain store, no lane-dependent branch), and the walker
+// keeps the lane index and byte range.  At the window end nothing but T is
+// looked at when T already is 255; else acc is reduced, and a parked lane is
+// reduced exactly only when its lane maximum (an upper bound of its part)
+// exceeds the rest of the window.
 struct RamWin {
     uint32_t acc;                        // per lane
-    int np;
-    PartLane* park;                      // two entries in LDS (per wave)
+    int32_t np, used;
+    int32_t l0, a0, b0, l1, a1, b1;
+    PartLane* park;                      // [2][kWave] entries in LDS (per walker)
 
     __device__ __forceinline__ void reset() {
         acc = 0;
         np = 0;
+        used = 0;
     }
     __device__ __forceinline__ void part(const uint4& v, uint32_t lm, int l,
                                          int32_t a_, int32_t b_) {
-        const Lane16 w = lane_words(v, l);
-        const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)lm, l);
-        if (lane_id() == 0)
-            park[np] = PartLane{make_uint4(w.d0, w.d1, w.d2, w.d3), a_, b_, u, 0};
+        park[np * kWave + lane_id()] = PartLane{v, 0, 0, lm, 0};
+        if (np == 0) {
+            l0 = l;
+            a0 = a_;
+            b0 = b_;
+        } else {
+            l1 = l;
+            a1 = a_;
+            b1 = b_;
+        }
         np++;
     }
+    __device__ __forceinline__ uint32_t parked(uint32_t T, int k, int l,
+                                               int a, int b) const {
+        const PartLane& e = park[k * kWave + l];
+        const uint32_t ub = uni(e.ub);
+        if (ub <= T) return T;
+        const Lane16 q{uni(e.q.x), uni(e.q.y), uni(e.q.z), uni(e.q.w)};
+        return max(T, lane_range_max(q, a, b));
+    }
     __device__ __forceinline__ uint32_t finish(uint32_t T) {
-        T = max(T, uni(wave_max(acc)));
-        for (int i = 0; i < np; i++) {
-            const PartLane p = park[i];
-            const uint32_t ub = uni(p.ub);
-            if (ub > T) {
-                const Lane16 q{uni(p.q.x), uni(p.q.y), uni(p.q.z), uni(p.q.w)};
-                T = max(T, lane_range_max(q, (int)uni((uint32_t)p.a), (int)uni((uint32_t)p.b)));
-            }
-        }
+        if (T >= 255) return T;
+        if (used) T = max(T, uni(wave_max(acc)));
+        if (np > 0) T = parked(T, 0, l0, a0, b0);
+        if (np > 1) T = parked(T, 1, l1, a1, b1);
         return T;
     }
 };
@@ -352,7 +365,10 @@ __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
             } else if (fl > fh) {        // inside one lane
                 X.part(v, lm, fh, lo_t & 15, hi_t & 15);
             } else {
-                if (fl < fh && lane >= fl && lane < fh) X.acc = max(X.acc, lm);
+                if (fl < fh) {
+                    if (lane >= fl && lane < fh) X.acc = max(X.acc, lm);
+                    X.used = 1;
+                }
                 if (lo_t & 15) X.part(v, lm, fl - 1, lo_t & 15, 16);
                 if (hi_t & 15) X.part(v, lm, fh, 0, hi_t & 15);
             }
@@ -537,19 +553,137 @@ __device__ __forceinline__ void run_tiles(const Source& src, Ring<G>& R,
     }
 }
 
-// Run one walker of the job from chunk start `start` (relative to base).
-template <bool RAM, bool INV, int G, class Emit>
-__device__ __forceinline__ void walk(const JobView& J, const Ctx& C,
-                                     Ring<G>& R, int64_t base, int32_t start,
-                                     Emit& emit, uint32_t* err) {
+// Cooperative streaming: a workgroup of two waves per walker.  Wave 0 (the
+// producer) loads tiles and stages them with their lane and tile maxima in
+// one half of a double-buffered LDS ring, while wave 1 (the walker) runs the
+// chain over the other half; the two halves swap at a workgroup barrier
+// every G tiles.  The producer's vector work then no longer sits in the
+// walker's instruction stream (a wave issues at most one instruction per
+// issue cycle of its SIMD; the two waves sit on different SIMDs).  The
+// walker decides when to stop and says so in LDS; both waves read that flag
+// after each barrier, and a final barrier keeps the next walk from touching
+// the ring before both have left.  The walker's tile budget (a hard stop one
+// tile past the job) bounds the loop.
+template <int G>
+struct Coop {
+    static constexpr bool kCoop = true;
+    uint4 t[2][G][kWave];
+    uint32_t lm[2][G][kWave];
+    uint64_t tmx[2][(G + 7) / 8];
+    PartLane park[2 * kWave];
+    int32_t done;
+};
+
+// The wave's role, as a uniform value (the compiler cannot tell on its own
+// that threadIdx.x / 64 is the same across a wave).
+__device__ __forceinline__ uint32_t wave_in_block() {
+    return uni(threadIdx.x >> 6);
+}
+__device__ __forceinline__ bool walker_wave(bool coop) {
+    return !coop || wave_in_block() == 1;
+}
+
+template <int G>
+__device__ __forceinline__ void coop_stage(Coop<G>& L, int slot,
+                                           const uint4 (&c)[G]) {
+    uint32_t lm[G], tm[G];
+#pragma unroll
+    for (int i = 0; i < G; i++) lm[i] = lane_max16(c[i]);
+#pragma unroll
+    for (int i = 0; i < G; i++) tm[i] = wave_max(lm[i]);
+#pragma unroll
+    for (int i = 0; i < G; i++) {
+        L.t[slot][i][lane_id()] = c[i];
+        L.lm[slot][i][lane_id()] = lm[i];
+    }
+#pragma unroll
+    for (int k = 0; k < (G + 7) / 8; k++) {
+        uint64_t p = 0;
+#pragma unroll
+        for (int i = 0; i < 8 && 8 * k + i < G; i++) p |= (uint64_t)tm[8 * k + i] << (8 * i);
+        if (lane_id() == 0) L.tmx[slot][k] = p;
+    }
+}
+
+template <bool INV, int G, class Body>
+__device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
+                                         int64_t base, int32_t first_rel,
+                                         int64_t n, Body&& body,
+                                         uint32_t* err) {
+    const bool prod = wave_in_block() == 0;
+    const int64_t t0 = src.tile_of(base + first_rel);
+    int32_t left = (int32_t)min(src.tile_of(n) + 2 - t0, (int64_t)0x7FFFFFFF);
+    int32_t tp = (int32_t)(src.tile_pos(t0) - base);
+    const uint4* p = src.base + t0 * kWave + lane_id();
+    int64_t rem = (int64_t)src.ngran - t0 * kWave;
+    uint4 c[G];
+    if (prod) {
+#pragma unroll
+        for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
+        coop_stage(L, 0, c);
+        p += kWave * G;
+        rem -= kWave * G;
+#pragma unroll
+        for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
+    } else if (lane_id() == 0) {
+        L.done = 0;
+    }
+    __syncthreads();
+    for (int g = 0;; g++) {
+        const int slot = g & 1;
+        if (prod) {
+            coop_stage(L, slot ^ 1, c);  // group g+1
+            p += kWave * G;
+            rem -= kWave * G;
+#pragma unroll
+            for (int i = 0; i < G; i++)
+                c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
+        } else {
+            uint64_t tmx[(G + 7) / 8];
+#pragma unroll
+            for (int k = 0; k < (G + 7) / 8; k++) tmx[k] = (uint64_t)uni64((int64_t)L.tmx[slot][k]);
+            bool fin = false;
+            for (int i = 0; i < G; i++) {
+                if (--left < 0) {
+                    if (lane_id() == 0) atomicOr(err, kErrOverflow);
+                    fin = true;
+                    break;
+                }
+                Tile t;
+                t.vp = &L.t[slot][i][lane_id()];
+                t.lmp = &L.lm[slot][i][lane_id()];
+                t.tp = tp;
+                t.tmax = (uint32_t)(tmx[i >> 3] >> (8 * (i & 7))) & 0xFFu;
+                if (body(t)) {
+                    fin = true;
+                    break;
+                }
+                tp += kTile;
+            }
+            if (fin && lane_id() == 0) L.done = 1;
+        }
+        __syncthreads();
+        if (uni((uint32_t)L.done)) break;
+    }
+    __syncthreads();
+}
+
+// Run one walker of the job from chunk start `start` (relative to base),
+// fed by one wave's own staging ring or by a cooperative producer wave (all
+// waves of the workgroup call this alike; only the walker wave emits).
+template <bool RAM, bool INV, class Stage, class Emit>
+__device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
+                                     int64_t base, int32_t start, Emit& emit,
+                                     uint32_t* err) {
+    constexpr bool kCoop = Stage::kCoop;
     Walker W;
     RamWin X;
-    X.park = R.park;
+    X.park = S.park;
     X.reset();
     if (RAM) {
         int32_t end;
         if (ram_start(W, C, start, &end)) {
-            emit(end);
+            if (walker_wave(kCoop)) emit(end);
             return;
         }
     } else {
@@ -557,14 +691,16 @@ __device__ __forceinline__ void walk(const JobView& J, const Ctx& C,
     }
     Source src;
     src.init(J.data, (uint64_t)J.n);
-    run_tiles<INV>(src, R, base, start, J.n,
-                   [&](const Tile& t) -> bool {
-                       if constexpr (RAM)
-                           return ram_tile(W, X, C, t, emit);
-                       else
-                           return ae_tile(W, C, t, emit);
-                   },
-                   err);
+    auto body = [&](const Tile& t) -> bool {
+        if constexpr (RAM)
+            return ram_tile(W, X, C, t, emit);
+        else
+            return ae_tile(W, C, t, emit);
+    };
+    if constexpr (kCoop)
+        run_coop<INV>(src, S, base, start, J.n, body, err);
+    else
+        run_tiles<INV>(src, S, base, start, J.n, body, err);
 }
 
 // ------------------------------------------------------------ lists
@@ -639,9 +775,11 @@ __device__ __forceinline__ uint32_t* list_of(const JobView& J,
 
 // ------------------------------------------------------------ speculate
 
-template <bool RAM, bool INV>
+// All waves of the workgroup call this alike; the walker wave records.
+template <bool RAM, bool INV, class Stage>
 __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
-                          const ChainWs& ws, Ring<kGroup>& R) {
+                          const ChainWs& ws, Stage& R) {
+    const bool rec = walker_wave(Stage::kCoop);
     const int64_t a = (int64_t)seg * J.seg;
     const Ctx C = ctx_of(J, a);
     const int32_t b = (int32_t)(min(J.n, a + J.seg) - a);
@@ -654,6 +792,7 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
         return c >= b;
     };
     walk<RAM, INV>(J, C, R, a, 0, emit, ws.err);
+    if (!rec) return;
     out.finish();
     if (lane_id() == 0) {
         SegMeta& m = ws.meta[item];
@@ -670,10 +809,12 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
 // the cuts before that are written to the fix-up list (fix-up round) or the
 // re-walk list.  Records the resolution (entry, pieces, count, exit) and
 // returns its exit.
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, class Stage>
 __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
                                 int64_t X, bool fixup, const ChainWs& ws,
-                                Ring<kGroupSolo>& R) {
+                                Stage& R) {
+    // all waves of the workgroup decide alike; the walker wave records
+    const bool rec = walker_wave(Stage::kCoop);
     const int64_t a = (int64_t)seg * J.seg;
     const Ctx C = ctx_of(J, a);
     const int32_t b = (int32_t)(min(J.n, a + J.seg) - a);
@@ -694,7 +835,7 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
     auto add = [&](uint32_t list, uint32_t lo, uint32_t hi) {
         hi = min(hi, J.cap);             // a list never holds more (else flagged)
         if (hi > lo) {
-            if (lane_id() == 0) m.pieces[np] = Piece{list, lo, hi};
+            if (rec && lane_id() == 0) m.pieces[np] = Piece{list, lo, hi};
             np++;
             count += hi - lo;
         }
@@ -778,10 +919,11 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
             return false;
         };
         walk<RAM, INV>(J, C, R, a, e, emit, ws.err);
+        if (!rec) return 0;
         wl.finish();
         new_nfix = min(wl.n, J.cap);
     }
-    if (lane_id() == 0) {
+    if (rec && lane_id() == 0) {
         if (fixup) {
             m.nfix = new_nfix;
             m.fms = new_fms;
@@ -797,57 +939,66 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
 
 // ------------------------------------------------------------ kernels
 
-// Per-item kernels walk the items grid-stride, one wave per item.
+// The per-item kernels walk the items grid-stride, one workgroup of two
+// waves (producer and walker) per item.
+constexpr int kCoopThreads = 2 * kWave;
+
+__device__ __forceinline__ bool coop_item(const Plan& P, uint32_t want,
+                                          uint32_t wid, JobView& J,
+                                          uint32_t& seg) {
+    return item_of(P, wid, J, seg) && J.ok && J.algo == want;
+}
+
 template <bool RAM, bool INV>
-__global__ __launch_bounds__(256) void k_spec(Plan P, ChainWs ws) {
-    __shared__ Ring<kGroup> lds[4];
+__global__ __launch_bounds__(kCoopThreads) void k_spec(Plan P, ChainWs ws) {
+    __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const uint32_t count = item_count(P);
-    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
         JobView J;
         uint32_t seg;
-        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
-        speculate<RAM, INV>(J, seg, wid, ws, lds[threadIdx.x / kWave]);
+        if (!coop_item(P, want, wid, J, seg)) continue;
+        speculate<RAM, INV>(J, seg, wid, ws, lds);
     }
 }
 
 // Fix-up round: every segment from the previous segment's speculative exit
 // (segment 0 from the job start).
 template <bool RAM, bool INV>
-__global__ __launch_bounds__(64) void k_fix(Plan P, ChainWs ws) {
-    __shared__ Ring<kGroupSolo> lds[1];
+__global__ __launch_bounds__(kCoopThreads) void k_fix(Plan P, ChainWs ws) {
+    __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const uint32_t count = item_count(P);
-    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
         JobView J;
         uint32_t seg;
-        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
+        if (!coop_item(P, want, wid, J, seg)) continue;
         const int64_t X = seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
-        const int64_t h = resolve_from<RAM, INV>(J, seg, wid, X, true, ws, lds[0]);
-        if (lane_id() == 0) ws.meta[wid].xo[1] = (uint64_t)h;
+        const int64_t h = resolve_from<RAM, INV>(J, seg, wid, X, true, ws, lds);
+        if (walker_wave(true) && lane_id() == 0) ws.meta[wid].xo[1] = (uint64_t)h;
     }
 }
 
 // Parallel round r >= 2: a segment whose predecessor's exit (as of round
 // r-1) differs from the entry it was resolved from is resolved again.
 template <bool RAM, bool INV>
-__global__ __launch_bounds__(64) void k_round(Plan P, ChainWs ws, int r) {
-    __shared__ Ring<kGroupSolo> lds[1];
+__global__ __launch_bounds__(kCoopThreads) void k_round(Plan P, ChainWs ws, int r) {
+    __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const uint32_t count = item_count(P);
     const int src = (r - 1) & 1, dst = r & 1;
-    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
         JobView J;
         uint32_t seg;
-        if (!item_of(P, wid, J, seg) || !J.ok || J.algo != want) continue;
+        if (!coop_item(P, want, wid, J, seg)) continue;
         SegMeta& m = ws.meta[wid];
         int64_t h = uni64((int64_t)m.rexit);
         if (seg > 0) {
             const int64_t X = uni64((int64_t)ws.meta[wid - 1].xo[src]);
             if (X != uni64((int64_t)m.entry))
-                h = resolve_from<RAM, INV>(J, seg, wid, X, false, ws, lds[0]);
+                h = resolve_from<RAM, INV>(J, seg, wid, X, false, ws, lds);
         }
-        if (lane_id() == 0) m.xo[dst] = (uint64_t)h;
+        if (walker_wave(true) && lane_id() == 0) m.xo[dst] = (uint64_t)h;
     }
 }
 
@@ -1006,13 +1157,12 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
                         const ChainWs& ws, int wpb, hipStream_t st, Marks* mk,
                         const char* spec_name) {
-    const dim3 blk(kWave * wpb), grid((items_upper + wpb - 1) / wpb);
+    (void)wpb;
+    const dim3 blk(kCoopThreads), grid(items_upper);
     CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV>), grid, blk, 0, st, P, ws);
-    CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV>), dim3(items_upper),
-               dim3(kWave), 0, st, P, ws);
+    CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV>), grid, blk, 0, st, P, ws);
     for (int r = 2; r < 2 + kRounds; r++)
-        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV>), dim3(items_upper),
-                   dim3(kWave), 0, st, P, ws, r);
+        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV>), grid, blk, 0, st, P, ws, r);
     CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
                dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
                n_jobs_d, ws);
