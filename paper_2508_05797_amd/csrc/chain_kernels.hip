@@ -31,6 +31,7 @@
 
 namespace cdc {
 
+constexpr int kSpan = 8;         // tiles a walker considers at once (one word of maxima)
 constexpr int kGroup = 8;        // tiles staged per step (speculation)
 constexpr int kGroupSolo = 16;   // same for the lone fix-up / re-walk walkers
 
@@ -154,6 +155,7 @@ struct PartLane {
 // room for a RAM window's partly covered lanes.
 template <int G>
 struct Ring {
+    static_assert(G % kSpan == 0, "whole spans per ring");
     static constexpr bool kCoop = false;
     uint4 t[G][kWave];
     uint32_t lm[G][kWave];
@@ -171,6 +173,38 @@ struct Tile {
     __device__ __forceinline__ uint4 v() const { return *vp; }
     __device__ __forceinline__ uint32_t lm() const { return *lmp; }
 };
+
+// Eight consecutive staged tiles from position gp: the walkers decide from
+// the packed tile maxima which tiles they can pass without looking inside.
+struct Group {
+    const uint4* vp;                     // this lane's piece of tile 0
+    const uint32_t* lmp;                 // this lane's maximum of tile 0
+    int32_t gp;
+    uint64_t tmx;                        // byte i: largest byte of tile i
+    __device__ __forceinline__ uint32_t tmax(int i) const {
+        return (uint32_t)(tmx >> (8 * i)) & 0xFFu;
+    }
+    __device__ __forceinline__ Tile tile(int i) const {
+        Tile t;
+        t.vp = vp + i * kWave;
+        t.lmp = lmp + i * kWave;
+        t.tp = gp + i * kTile;
+        t.tmax = tmax(i);
+        return t;
+    }
+};
+
+// Index of the first tile i >= k of the group whose largest byte is >= T
+// (1 <= T <= 255), kSpan if there is none; the packed maxima are compared
+// as in ge_bytes.
+__device__ __forceinline__ int32_t first_tile_ge(uint64_t tmx, int32_t k,
+                                                 uint32_t T) {
+    const uint64_t H = 0x8080808080808080ull;
+    const uint64_t y = (uint64_t)(T * 0x01010101u) * 0x100000001ull;
+    const uint64_t r = (tmx | H) - (y & ~H);
+    const uint64_t g = ((tmx & ~y) | (~(tmx ^ y) & r)) & H & bytes_from(k);
+    return g ? (int32_t)(__builtin_ctzll(g) >> 3) : kSpan;
+}
 
 // Largest byte M among positions [lo, hi) of the tile (lo < hi, both inside)
 // and, in *pos, the first position holding it.  The partly covered first
@@ -292,7 +326,7 @@ __device__ __forceinline__ void ae_start(Walker& W, const Ctx& C, int32_t c) {
 struct RamWin {
     uint32_t acc;                        // per lane
     int32_t np, used;
-    int32_t l0, a0, b0, l1, a1, b1;
+    uint32_t p0, p1;                     // parked lane | first byte << 8 | end << 16
     PartLane* park;                      // [2][kWave] entries in LDS (per walker)
 
     __device__ __forceinline__ void reset() {
@@ -303,55 +337,37 @@ struct RamWin {
     __device__ __forceinline__ void part(const uint4& v, uint32_t lm, int l,
                                          int32_t a_, int32_t b_) {
         park[np * kWave + lane_id()] = PartLane{v, 0, 0, lm, 0};
-        if (np == 0) {
-            l0 = l;
-            a0 = a_;
-            b0 = b_;
-        } else {
-            l1 = l;
-            a1 = a_;
-            b1 = b_;
-        }
+        const uint32_t d = (uint32_t)l | ((uint32_t)a_ << 8) | ((uint32_t)b_ << 16);
+        if (np == 0)
+            p0 = d;
+        else
+            p1 = d;
         np++;
     }
-    __device__ __forceinline__ uint32_t parked(uint32_t T, int k, int l,
-                                               int a, int b) const {
-        const PartLane& e = park[k * kWave + l];
+    __device__ __forceinline__ uint32_t parked(uint32_t T, int k,
+                                               uint32_t d) const {
+        const PartLane& e = park[k * kWave + (int)(d & 255u)];
         const uint32_t ub = uni(e.ub);
         if (ub <= T) return T;
         const Lane16 q{uni(e.q.x), uni(e.q.y), uni(e.q.z), uni(e.q.w)};
-        return max(T, lane_range_max(q, a, b));
+        return max(T, lane_range_max(q, (int)((d >> 8) & 255u), (int)(d >> 16)));
     }
     __device__ __forceinline__ uint32_t finish(uint32_t T) {
         if (T >= 255) return T;
         if (used) T = max(T, uni(wave_max(acc)));
-        if (np > 0) T = parked(T, 0, l0, a0, b0);
-        if (np > 1) T = parked(T, 1, l1, a1, b1);
+        if (np > 0) T = parked(T, 0, p0);
+        if (np > 1) T = parked(T, 1, p1);
         return T;
     }
 };
 
-// Advance a RAM walker over a tile.  emit(c) is called for every chunk end
-// c and returns true to stop the walker; returns true once stopped.  A tile
-// that only continues a window, or that a scan crosses without a hit, costs
-// a few scalar compares on its maximum.
+// Advance a RAM walker through the rest of a tile (from W.cur, inside it).
+// emit(c) is called for every chunk end c and returns true to stop the
+// walker; returns true once stopped.
 template <class Emit>
 __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
                                          const Tile& t, Emit& emit) {
     const int32_t tp = t.tp, te = tp + kTile;
-    if (W.cur >= te) return false;
-    if (W.cur == tp) {                   // continuing from the previous tile
-        if (!W.scan) {
-            if (W.we > te) {             // the whole tile is window
-                W.T = max(W.T, (int32_t)t.tmax);
-                W.cur = te;
-                return false;
-            }
-        } else if (W.L > te && (int32_t)t.tmax < W.T) {
-            W.cur = te;                  // no byte >= T, no limit here
-            return false;
-        }
-    }
     const uint4 v = t.v();
     const uint32_t lm = t.lm();
     const int32_t lane = (int32_t)lane_id();
@@ -366,7 +382,8 @@ __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
                 X.part(v, lm, fh, lo_t & 15, hi_t & 15);
             } else {
                 if (fl < fh) {
-                    if (lane >= fl && lane < fh) X.acc = max(X.acc, lm);
+                    const bool in = lane >= fl && lane < fh;
+                    X.acc = in ? max(X.acc, lm) : X.acc;
                     X.used = 1;
                 }
                 if (lo_t & 15) X.part(v, lm, fl - 1, lo_t & 15, 16);
@@ -410,17 +427,39 @@ __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
     }
 }
 
-// Advance an AE walker over a tile (as ram_tile).
+// Advance a RAM walker over a group.  At a tile start, the tiles that lie
+// wholly inside the window only raise T by their maxima, and the tiles a
+// scan crosses without a byte >= T and without reaching the limit are
+// passed; the walker looks inside a tile only where a window ends or a scan
+// can stop.
+template <class Emit>
+__device__ __forceinline__ bool ram_group(Walker& W, RamWin& X, const Ctx& C,
+                                          const Group& g, Emit& emit) {
+    const int32_t gp = g.gp;
+    for (;;) {
+        int32_t i = (W.cur - gp) >> 10;
+        if (i >= kSpan) return false;
+        if (W.cur == gp + i * kTile) {
+            if (!W.scan) {
+                const int32_t kw = min(kSpan, (W.we - 1 - gp) >> 10);
+                for (; i < kw; i++) W.T = max(W.T, (int32_t)g.tmax(i));
+            } else if (W.T > 0) {
+                const int32_t k = min(first_tile_ge(g.tmx, i, (uint32_t)W.T),
+                                      (W.L - 1 - gp) >> 10);
+                i = max(i, k);
+            }
+            W.cur = gp + i * kTile;
+            if (i >= kSpan) return false;
+        }
+        if (ram_tile(W, X, C, g.tile(i), emit)) return true;
+    }
+}
+
+// Advance an AE walker through the rest of a tile (as ram_tile).
 template <class Emit>
 __device__ __forceinline__ bool ae_tile(Walker& W, const Ctx& C, const Tile& t,
                                         Emit& emit) {
     const int32_t tp = t.tp, te = tp + kTile;
-    if (W.cur >= te) return false;
-    if (W.cur == tp && W.T >= 0 && min(W.we + C.w + 1, W.L) > te &&
-        (int32_t)t.tmax < W.T) {
-        W.cur = te;                      // nothing in the tile exceeds the target
-        return false;
-    }
     const uint4 v = t.v();
     const uint32_t lm = t.lm();
     for (;;) {
@@ -465,6 +504,30 @@ __device__ __forceinline__ bool ae_tile(Walker& W, const Ctx& C, const Tile& t,
         if (emit(wend)) return true;
         ae_start(W, C, wend);
         if (W.cur >= te) return false;
+    }
+}
+
+// Advance an AE walker over a group: at a tile start, tiles before the one
+// where the target's window ends and without a byte above the target are
+// passed.
+template <class Emit>
+__device__ __forceinline__ bool ae_group(Walker& W, const Ctx& C,
+                                         const Group& g, Emit& emit) {
+    const int32_t gp = g.gp;
+    for (;;) {
+        int32_t i = (W.cur - gp) >> 10;
+        if (i >= kSpan) return false;
+        if (W.cur == gp + i * kTile && W.T >= 0) {
+            // the window can end right here (a target on the previous
+            // tile's last byte with the limit at this tile's start): then
+            // nothing is passed
+            const int32_t kl = (min(W.we + C.w + 1, W.L) - 1 - gp) >> 10;
+            const int32_t kf = W.T > 255 ? kSpan : first_tile_ge(g.tmx, i, (uint32_t)W.T);
+            i = max(i, min(kf, kl));
+            W.cur = gp + i * kTile;
+            if (i >= kSpan) return false;
+        }
+        if (ae_tile(W, C, g.tile(i), emit)) return true;
     }
 }
 
@@ -513,8 +576,9 @@ __device__ __forceinline__ void stage(Ring<G>& R, const uint4 (&c)[G],
 
 // Streams tiles from the one holding position first_rel (relative to base):
 // G tiles are loaded into registers while the previous G are processed from
-// the LDS ring.  body(tile) returns true when the wave is done.  A hard stop
-// one tile past the end of the job guarantees every wave exits.
+// the LDS ring, kSpan at a time.  body(group) returns true when the wave is
+// done.  A hard stop one group past the end of the job guarantees every wave
+// exits.
 template <bool INV, int G, class Body>
 __device__ __forceinline__ void run_tiles(const Source& src, Ring<G>& R,
                                           int64_t base, int32_t first_rel,
@@ -536,18 +600,16 @@ __device__ __forceinline__ void run_tiles(const Source& src, Ring<G>& R,
 #pragma unroll
         for (int i = 0; i < G; i++)
             c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
-        for (int i = 0; i < G; i++) {
-            if (--left < 0) {
+        for (int h = 0; h < G / kSpan; h++) {
+            if (left <= 0) {
                 if (lane_id() == 0) atomicOr(err, kErrOverflow);
                 return;
             }
-            Tile t;
-            t.vp = &R.t[i][lane_id()];
-            t.lmp = &R.lm[i][lane_id()];
-            t.tp = tp;
-            t.tmax = (uint32_t)(tmx[i >> 3] >> (8 * (i & 7))) & 0xFFu;
-            if (body(t)) return;
-            tp += kTile;
+            left -= kSpan;
+            const Group gr{&R.t[h * kSpan][lane_id()], &R.lm[h * kSpan][lane_id()],
+                           tp, tmx[h]};
+            if (body(gr)) return;
+            tp += kSpan * kTile;
         }
         stage(R, c, tmx);
     }
@@ -562,16 +624,21 @@ __device__ __forceinline__ void run_tiles(const Source& src, Ring<G>& R,
 // issue cycle of its SIMD; the two waves sit on different SIMDs).  The
 // walker decides when to stop and says so in LDS; both waves read that flag
 // after each barrier, and a final barrier keeps the next walk from touching
-// the ring before both have left.  The walker's tile budget (a hard stop one
-// tile past the job) bounds the loop.
+// the ring before both have left.  The flag of group g sits in done[g & 1],
+// so the walker's write for the next group can never be seen by a producer
+// still reading the current one.  Each role has a loop of its own (so that
+// the other role's state is not live in it); both pass the same number of
+// barriers.  The walker's tile budget (a hard stop one tile past the job)
+// bounds the loop.
 template <int G>
 struct Coop {
+    static_assert(G % kSpan == 0, "whole spans per ring half");
     static constexpr bool kCoop = true;
     uint4 t[2][G][kWave];
     uint32_t lm[2][G][kWave];
     uint64_t tmx[2][(G + 7) / 8];
     PartLane park[2 * kWave];
-    int32_t done;
+    int32_t done[2];
 };
 
 // The wave's role, as a uniform value (the compiler cannot tell on its own
@@ -610,14 +677,11 @@ __device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
                                          int64_t base, int32_t first_rel,
                                          int64_t n, Body&& body,
                                          uint32_t* err) {
-    const bool prod = wave_in_block() == 0;
     const int64_t t0 = src.tile_of(base + first_rel);
-    int32_t left = (int32_t)min(src.tile_of(n) + 2 - t0, (int64_t)0x7FFFFFFF);
-    int32_t tp = (int32_t)(src.tile_pos(t0) - base);
-    const uint4* p = src.base + t0 * kWave + lane_id();
-    int64_t rem = (int64_t)src.ngran - t0 * kWave;
-    uint4 c[G];
-    if (prod) {
+    if (wave_in_block() == 0) {          // producer
+        const uint4* p = src.base + t0 * kWave + lane_id();
+        int64_t rem = (int64_t)src.ngran - t0 * kWave;
+        uint4 c[G];
 #pragma unroll
         for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
         coop_stage(L, 0, c);
@@ -625,45 +689,44 @@ __device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
         rem -= kWave * G;
 #pragma unroll
         for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
-    } else if (lane_id() == 0) {
-        L.done = 0;
-    }
-    __syncthreads();
-    for (int g = 0;; g++) {
-        const int slot = g & 1;
-        if (prod) {
-            coop_stage(L, slot ^ 1, c);  // group g+1
+        __syncthreads();
+        for (int g = 0;; g++) {
+            coop_stage(L, (g & 1) ^ 1, c);   // group g+1
             p += kWave * G;
             rem -= kWave * G;
 #pragma unroll
             for (int i = 0; i < G; i++)
                 c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
-        } else {
-            uint64_t tmx[(G + 7) / 8];
-#pragma unroll
-            for (int k = 0; k < (G + 7) / 8; k++) tmx[k] = (uint64_t)uni64((int64_t)L.tmx[slot][k]);
-            bool fin = false;
-            for (int i = 0; i < G; i++) {
-                if (--left < 0) {
-                    if (lane_id() == 0) atomicOr(err, kErrOverflow);
-                    fin = true;
-                    break;
-                }
-                Tile t;
-                t.vp = &L.t[slot][i][lane_id()];
-                t.lmp = &L.lm[slot][i][lane_id()];
-                t.tp = tp;
-                t.tmax = (uint32_t)(tmx[i >> 3] >> (8 * (i & 7))) & 0xFFu;
-                if (body(t)) {
-                    fin = true;
-                    break;
-                }
-                tp += kTile;
-            }
-            if (fin && lane_id() == 0) L.done = 1;
+            __syncthreads();
+            if (uni((uint32_t)L.done[g & 1])) break;
         }
+    } else {                             // walker
+        int32_t left = (int32_t)min(src.tile_of(n) + 2 - t0, (int64_t)0x7FFFFFFF);
+        int32_t tp = (int32_t)(src.tile_pos(t0) - base);
         __syncthreads();
-        if (uni((uint32_t)L.done)) break;
+        for (int g = 0;; g++) {
+            const int slot = g & 1;
+            uint32_t fin = 0;
+            for (int h = 0; h < G / kSpan; h++) {
+                if (left <= 0) {
+                    if (lane_id() == 0) atomicOr(err, kErrOverflow);
+                    fin = 1;
+                    break;
+                }
+                left -= kSpan;
+                const Group gr{&L.t[slot][h * kSpan][lane_id()],
+                               &L.lm[slot][h * kSpan][lane_id()], tp,
+                               (uint64_t)uni64((int64_t)L.tmx[slot][h])};
+                if (body(gr)) {
+                    fin = 1;
+                    break;
+                }
+                tp += kSpan * kTile;
+            }
+            if (lane_id() == 0) L.done[slot] = (int32_t)fin;
+            __syncthreads();
+            if (fin) break;
+        }
     }
     __syncthreads();
 }
@@ -691,11 +754,11 @@ __device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
     }
     Source src;
     src.init(J.data, (uint64_t)J.n);
-    auto body = [&](const Tile& t) -> bool {
+    auto body = [&](const Group& g) -> bool {
         if constexpr (RAM)
-            return ram_tile(W, X, C, t, emit);
+            return ram_group(W, X, C, g, emit);
         else
-            return ae_tile(W, C, t, emit);
+            return ae_group(W, C, g, emit);
     };
     if constexpr (kCoop)
         run_coop<INV>(src, S, base, start, J.n, body, err);
@@ -939,58 +1002,57 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
 
 // ------------------------------------------------------------ kernels
 
-// The per-item kernels walk the items grid-stride, one workgroup of two
-// waves (producer and walker) per item.
+// The per-item kernels run one workgroup of two waves (producer and walker)
+// per item: with one job the grid covers its segments (one each); with a
+// job table the workgroups walk the item table grid-stride.
 constexpr int kCoopThreads = 2 * kWave;
 
-__device__ __forceinline__ bool coop_item(const Plan& P, uint32_t want,
-                                          uint32_t wid, JobView& J,
-                                          uint32_t& seg) {
-    return item_of(P, wid, J, seg) && J.ok && J.algo == want;
+template <bool ONE, class F>
+__device__ __forceinline__ void for_items(const Plan& P, uint32_t want, F&& f) {
+    if constexpr (ONE) {
+        const uint32_t wid = uni(blockIdx.x);
+        if (wid >= P.one_items) return;
+        const JobView J = view(P.one);
+        if (J.ok && J.algo == want) f(J, wid, wid);
+    } else {
+        for (uint32_t wid = uni(blockIdx.x); wid < uni(*P.n_items); wid += gridDim.x) {
+            const Item it = P.items[wid];
+            const JobView J = view(P.jobs[uni(it.job)]);
+            if (J.ok && J.algo == want) f(J, uni(it.seg), wid);
+        }
+    }
 }
 
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_spec(Plan P, ChainWs ws) {
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    const uint32_t count = item_count(P);
-    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
-        JobView J;
-        uint32_t seg;
-        if (!coop_item(P, want, wid, J, seg)) continue;
+    for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
         speculate<RAM, INV>(J, seg, wid, ws, lds);
-    }
+    });
 }
 
 // Fix-up round: every segment from the previous segment's speculative exit
 // (segment 0 from the job start).
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_fix(Plan P, ChainWs ws) {
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    const uint32_t count = item_count(P);
-    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
-        JobView J;
-        uint32_t seg;
-        if (!coop_item(P, want, wid, J, seg)) continue;
+    for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
         const int64_t X = seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
         const int64_t h = resolve_from<RAM, INV>(J, seg, wid, X, true, ws, lds);
         if (walker_wave(true) && lane_id() == 0) ws.meta[wid].xo[1] = (uint64_t)h;
-    }
+    });
 }
 
 // Parallel round r >= 2: a segment whose predecessor's exit (as of round
 // r-1) differs from the entry it was resolved from is resolved again.
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_round(Plan P, ChainWs ws, int r) {
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    const uint32_t count = item_count(P);
     const int src = (r - 1) & 1, dst = r & 1;
-    for (uint32_t wid = uni(blockIdx.x); wid < count; wid += gridDim.x) {
-        JobView J;
-        uint32_t seg;
-        if (!coop_item(P, want, wid, J, seg)) continue;
+    for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
         SegMeta& m = ws.meta[wid];
         int64_t h = uni64((int64_t)m.rexit);
         if (seg > 0) {
@@ -999,7 +1061,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_round(Plan P, ChainWs ws, int 
                 h = resolve_from<RAM, INV>(J, seg, wid, X, false, ws, lds);
         }
         if (walker_wave(true) && lane_id() == 0) m.xo[dst] = (uint64_t)h;
-    }
+    });
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x <= 1024).
@@ -1152,17 +1214,29 @@ __global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
         if (MK) (MK)->end(LVL, st);                    \
     } while (0)
 
+template <bool RAM, bool INV, bool ONE>
+static void launch_passes(const Plan& P, uint32_t items_upper,
+                          const ChainWs& ws, hipStream_t st, Marks* mk,
+                          const char* spec_name) {
+    const dim3 blk(kCoopThreads), grid(items_upper);
+    CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+    CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+    for (int r = 2; r < 2 + kRounds; r++)
+        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
+}
+
+// With one job, items_upper is its segment count (the grid covers every
+// segment); with a job table the kernels walk the items grid-stride.
 template <bool RAM, bool INV>
 static void launch_algo(const Plan& P, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
                         const ChainWs& ws, int wpb, hipStream_t st, Marks* mk,
                         const char* spec_name) {
     (void)wpb;
-    const dim3 blk(kCoopThreads), grid(items_upper);
-    CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV>), grid, blk, 0, st, P, ws);
-    CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV>), grid, blk, 0, st, P, ws);
-    for (int r = 2; r < 2 + kRounds; r++)
-        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV>), grid, blk, 0, st, P, ws, r);
+    if (P.jobs == nullptr)
+        launch_passes<RAM, INV, true>(P, items_upper, ws, st, mk, spec_name);
+    else
+        launch_passes<RAM, INV, false>(P, items_upper, ws, st, mk, spec_name);
     CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
                dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
                n_jobs_d, ws);
