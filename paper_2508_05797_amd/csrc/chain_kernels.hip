@@ -144,22 +144,13 @@ __device__ __forceinline__ uint32_t lanes_max(uint32_t lm, int32_t l0,
 
 // ------------------------------------------------------------ tiles
 
-// One lane's bytes and lane maximum, parked for a RAM window.
-struct PartLane {
-    uint4 q;
-    int32_t a, b;
-    uint32_t ub, pad;
-};
-
-// Per-wave LDS staging: the bytes of G tiles and their lane maxima, and
-// room for a RAM window's partly covered lanes.
+// Per-wave LDS staging: the bytes of G tiles and their lane maxima.
 template <int G>
 struct Ring {
     static_assert(G % kSpan == 0, "whole spans per ring");
     static constexpr bool kCoop = false;
     uint4 t[G][kWave];
-    uint32_t lm[G][kWave];
-    PartLane park[2 * kWave];
+    uint8_t lm[G][kWave];
 };
 
 // A staged tile as a walker sees it: its position (relative to the segment
@@ -167,7 +158,7 @@ struct Ring {
 // in LDS and are read only where a chunk boundary falls into the tile.
 struct Tile {
     const uint4* vp;
-    const uint32_t* lmp;
+    const uint8_t* lmp;
     int32_t tp;
     uint32_t tmax;
     __device__ __forceinline__ uint4 v() const { return *vp; }
@@ -178,7 +169,7 @@ struct Tile {
 // the packed tile maxima which tiles they can pass without looking inside.
 struct Group {
     const uint4* vp;                     // this lane's piece of tile 0
-    const uint32_t* lmp;                 // this lane's maximum of tile 0
+    const uint8_t* lmp;                  // this lane's maximum of tile 0
     int32_t gp;
     uint64_t tmx;                        // byte i: largest byte of tile i
     __device__ __forceinline__ uint32_t tmax(int i) const {
@@ -315,49 +306,33 @@ __device__ __forceinline__ void ae_start(Walker& W, const Ctx& C, int32_t c) {
 }
 
 // Window maximum under construction (RAM): whole tiles go into the
-// walker's T; lanes wholly inside the window of its first and last tiles go
-// into acc (reduced once, where the window ends); for the at most two lanes
-// that the window covers only in part, every lane parks its bytes and lane
-// maximum in LDS (a plain store, no lane-dependent branch), and the walker
-// keeps the lane index and byte range.  At the window end nothing but T is
-// looked at when T already is 255; else acc is reduced, and a parked lane is
-// reduced exactly only when its lane maximum (an upper bound of its part)
-// exceeds the rest of the window.
+// walker's T; in the window's first and last tiles every lane folds the
+// maximum of its bytes inside the window into acc (a partly covered lane
+// masks its bytes, so no lane-dependent branch is taken), and acc is reduced
+// once, where the window ends, unless T already is 255.
 struct RamWin {
     uint32_t acc;                        // per lane
-    int32_t np, used;
-    uint32_t p0, p1;                     // parked lane | first byte << 8 | end << 16
-    PartLane* park;                      // [2][kWave] entries in LDS (per walker)
+    int32_t used;
 
     __device__ __forceinline__ void reset() {
         acc = 0;
-        np = 0;
         used = 0;
     }
-    __device__ __forceinline__ void part(const uint4& v, uint32_t lm, int l,
-                                         int32_t a_, int32_t b_) {
-        park[np * kWave + lane_id()] = PartLane{v, 0, 0, lm, 0};
-        const uint32_t d = (uint32_t)l | ((uint32_t)a_ << 8) | ((uint32_t)b_ << 16);
-        if (np == 0)
-            p0 = d;
+    // bytes [lo, hi) of the tile (offsets inside it, lo < hi)
+    __device__ __forceinline__ void add(const uint4& v, uint32_t lm, int32_t lo,
+                                        int32_t hi) {
+        const int32_t a = lo - 16 * (int32_t)lane_id(), b = hi - 16 * (int32_t)lane_id();
+        uint32_t m;
+        if ((lo | hi) & 15)              // some lane is covered in part
+            m = lane_max16(keep_bytes(v, a, b));
         else
-            p1 = d;
-        np++;
+            m = (a <= 0 && b >= 16) ? lm : 0u;
+        acc = max(acc, m);
+        used = 1;
     }
-    __device__ __forceinline__ uint32_t parked(uint32_t T, int k,
-                                               uint32_t d) const {
-        const PartLane& e = park[k * kWave + (int)(d & 255u)];
-        const uint32_t ub = uni(e.ub);
-        if (ub <= T) return T;
-        const Lane16 q{uni(e.q.x), uni(e.q.y), uni(e.q.z), uni(e.q.w)};
-        return max(T, lane_range_max(q, (int)((d >> 8) & 255u), (int)(d >> 16)));
-    }
-    __device__ __forceinline__ uint32_t finish(uint32_t T) {
-        if (T >= 255) return T;
-        if (used) T = max(T, uni(wave_max(acc)));
-        if (np > 0) T = parked(T, 0, p0);
-        if (np > 1) T = parked(T, 1, p1);
-        return T;
+    __device__ __forceinline__ uint32_t finish(uint32_t T) const {
+        if (T >= 255 || !used) return T;
+        return max(T, uni(wave_max(acc)));
     }
 };
 
@@ -370,25 +345,14 @@ __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
     const int32_t tp = t.tp, te = tp + kTile;
     const uint4 v = t.v();
     const uint32_t lm = t.lm();
-    const int32_t lane = (int32_t)lane_id();
     for (;;) {
         if (!W.scan) {
             // window bytes [cur, min(we, te)) of this tile
             const int32_t lo_t = W.cur - tp, hi_t = min(W.we, te) - tp;
-            const int32_t fl = (lo_t + 15) >> 4, fh = hi_t >> 4;
-            if (fl == 0 && fh == kWave) {
+            if (lo_t == 0 && hi_t == kTile)
                 W.T = max(W.T, (int32_t)t.tmax);
-            } else if (fl > fh) {        // inside one lane
-                X.part(v, lm, fh, lo_t & 15, hi_t & 15);
-            } else {
-                if (fl < fh) {
-                    const bool in = lane >= fl && lane < fh;
-                    X.acc = in ? max(X.acc, lm) : X.acc;
-                    X.used = 1;
-                }
-                if (lo_t & 15) X.part(v, lm, fl - 1, lo_t & 15, 16);
-                if (hi_t & 15) X.part(v, lm, fh, 0, hi_t & 15);
-            }
+            else
+                X.add(v, lm, lo_t, hi_t);
             if (W.we > te) {
                 W.cur = te;
                 return false;
@@ -563,7 +527,7 @@ __device__ __forceinline__ void stage(Ring<G>& R, const uint4 (&c)[G],
 #pragma unroll
     for (int i = 0; i < G; i++) {
         R.t[i][lane_id()] = c[i];
-        R.lm[i][lane_id()] = lm[i];
+        R.lm[i][lane_id()] = (uint8_t)lm[i];
     }
 #pragma unroll
     for (int k = 0; k < (G + 7) / 8; k++) {
@@ -635,9 +599,8 @@ struct Coop {
     static_assert(G % kSpan == 0, "whole spans per ring half");
     static constexpr bool kCoop = true;
     uint4 t[2][G][kWave];
-    uint32_t lm[2][G][kWave];
+    uint8_t lm[2][G][kWave];
     uint64_t tmx[2][(G + 7) / 8];
-    PartLane park[2 * kWave];
     int32_t done[2];
 };
 
@@ -661,7 +624,7 @@ __device__ __forceinline__ void coop_stage(Coop<G>& L, int slot,
 #pragma unroll
     for (int i = 0; i < G; i++) {
         L.t[slot][i][lane_id()] = c[i];
-        L.lm[slot][i][lane_id()] = lm[i];
+        L.lm[slot][i][lane_id()] = (uint8_t)lm[i];
     }
 #pragma unroll
     for (int k = 0; k < (G + 7) / 8; k++) {
@@ -741,7 +704,6 @@ __device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
     constexpr bool kCoop = Stage::kCoop;
     Walker W;
     RamWin X;
-    X.park = S.park;
     X.reset();
     if (RAM) {
         int32_t end;
