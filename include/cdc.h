@@ -157,9 +157,9 @@ const char* cdc_last_error(void);
 /*
  * Tuning knobs.  They change only speed, never the offsets.
  *   chain_segment    bytes per segment of the segment-parallel chain search
- *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 1 MiB);
+ *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 512 KiB);
  *   maxp_segment     bytes per MAXP work item (16 .. 2^28; 0: 64 KiB);
- *   waves_per_block  waves per workgroup of the speculation pass (1 .. 4;
+ *   waves_per_block  waves per workgroup of the MAXP and output passes (1 .. 4;
  *                    0: 4);
  *   reserved         must be 0.
  * A reservation (cdc_reserve) keeps the segment lengths it was made with.

@@ -61,7 +61,7 @@ struct SegMeta {
     uint32_t fms;            // speculative index the fix-up chain continues from, or kNone
     uint32_t count;          // cuts of the current resolution
     uint32_t npieces;
-    uint32_t pad;
+    uint32_t cval;           // RAM: 0x100 | v when every byte of the segment is v, else 0
     Piece pieces[3];
 };
 

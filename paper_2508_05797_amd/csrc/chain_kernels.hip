@@ -602,6 +602,7 @@ struct Coop {
     uint8_t lm[2][G][kWave];
     uint64_t tmx[2][(G + 7) / 8];
     int32_t done[2];
+    int32_t xfer[2];                     // walker -> producer (resolution)
 };
 
 // The wave's role, as a uniform value (the compiler cannot tell on its own
@@ -635,19 +636,45 @@ __device__ __forceinline__ void coop_stage(Coop<G>& L, int slot,
     }
 }
 
+// Constancy of the tiles staged from position tp (relative): for every tile
+// that starts before `end`, st stays the common byte value (0..255) while
+// each such tile holds one value throughout; -1 before the first such tile,
+// -2 once one differs.
+template <int G>
+__device__ __forceinline__ int32_t track_constant(const uint4 (&c)[G],
+                                                  int32_t tp, int32_t end,
+                                                  int32_t st) {
+#pragma unroll
+    for (int i = 0; i < G; i++) {
+        if (st == -2 || tp + i * kTile >= end) break;
+        const uint32_t v = (uint32_t)__builtin_amdgcn_readfirstlane((int)c[i].x) & 0xFFu;
+        const uint32_t b4 = v * 0x01010101u;
+        const bool eq = c[i].x == b4 && c[i].y == b4 && c[i].z == b4 && c[i].w == b4;
+        if (__ballot(eq) != ~0ull || (st >= 0 && (uint32_t)st != v))
+            st = -2;
+        else
+            st = (int32_t)v;
+    }
+    return st;
+}
+
 template <bool INV, int G, class Body>
-__device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
+__device__ __forceinline__ int32_t run_coop(const Source& src, Coop<G>& L,
                                          int64_t base, int32_t first_rel,
                                          int64_t n, Body&& body,
-                                         uint32_t* err) {
+                                         uint32_t* err, int32_t track_end) {
     const int64_t t0 = src.tile_of(base + first_rel);
+    int32_t cst = -1;
     if (wave_in_block() == 0) {          // producer
         const uint4* p = src.base + t0 * kWave + lane_id();
         int64_t rem = (int64_t)src.ngran - t0 * kWave;
+        int32_t ptp = (int32_t)(src.tile_pos(t0) - base);
         uint4 c[G];
 #pragma unroll
         for (int i = 0; i < G; i++) c[i] = ld_tile<INV>(p + kWave * i, lanes_valid(rem - kWave * i));
         coop_stage(L, 0, c);
+        if (track_end > 0) cst = track_constant(c, ptp, track_end, cst);
+        ptp += G * kTile;
         p += kWave * G;
         rem -= kWave * G;
 #pragma unroll
@@ -655,6 +682,8 @@ __device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
         __syncthreads();
         for (int g = 0;; g++) {
             coop_stage(L, (g & 1) ^ 1, c);   // group g+1
+            if (track_end > 0) cst = track_constant(c, ptp, track_end, cst);
+            ptp += G * kTile;
             p += kWave * G;
             rem -= kWave * G;
 #pragma unroll
@@ -692,15 +721,16 @@ __device__ __forceinline__ void run_coop(const Source& src, Coop<G>& L,
         }
     }
     __syncthreads();
+    return cst;
 }
 
 // Run one walker of the job from chunk start `start` (relative to base),
 // fed by one wave's own staging ring or by a cooperative producer wave (all
 // waves of the workgroup call this alike; only the walker wave emits).
 template <bool RAM, bool INV, class Stage, class Emit>
-__device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
-                                     int64_t base, int32_t start, Emit& emit,
-                                     uint32_t* err) {
+__device__ __forceinline__ int32_t walk(const JobView& J, const Ctx& C, Stage& S,
+                                        int64_t base, int32_t start, Emit& emit,
+                                        uint32_t* err, int32_t track_end = 0) {
     constexpr bool kCoop = Stage::kCoop;
     Walker W;
     RamWin X;
@@ -709,7 +739,7 @@ __device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
         int32_t end;
         if (ram_start(W, C, start, &end)) {
             if (walker_wave(kCoop)) emit(end);
-            return;
+            return -1;
         }
     } else {
         ae_start(W, C, start);
@@ -722,10 +752,12 @@ __device__ __forceinline__ void walk(const JobView& J, const Ctx& C, Stage& S,
         else
             return ae_group(W, C, g, emit);
     };
-    if constexpr (kCoop)
-        run_coop<INV>(src, S, base, start, J.n, body, err);
-    else
+    if constexpr (kCoop) {
+        return run_coop<INV>(src, S, base, start, J.n, body, err, track_end);
+    } else {
         run_tiles<INV>(src, S, base, start, J.n, body, err);
+        return -1;
+    }
 }
 
 // ------------------------------------------------------------ lists
@@ -816,8 +848,14 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
         last = c;
         return c >= b;
     };
-    walk<RAM, INV>(J, C, R, a, 0, emit, ws.err);
-    if (!rec) return;
+    // RAM: the producer also reports whether every byte of the segment is
+    // one value (for the arithmetic resolution below)
+    const int32_t cst = walk<RAM, INV>(J, C, R, a, 0, emit, ws.err, RAM ? b : 0);
+    if (!rec) {
+        if (RAM && lane_id() == 0)
+            ws.meta[item].cval = cst >= 0 ? 0x100u | (uint32_t)cst : 0u;
+        return;
+    }
     out.finish();
     if (lane_id() == 0) {
         SegMeta& m = ws.meta[item];
@@ -914,6 +952,12 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
     if (!settled) {
         CutList wl;
         wl.init(list_of(J, ws, seg, own), J.cap, ws.err);
+        // RAM over a segment of one byte value (or with max_chunk = w + 1):
+        // a chunk whose w + 1 bytes lie in the segment is exactly w + 1 long
+        // (its last byte equals the window maximum, or the forced cut falls
+        // there), so those cuts follow arithmetically; the walk resumes at
+        // the last of them.
+        const bool arith = RAM && (C.M == C.w + 1 || (uni(m.cval) & 0x100u));
         ListCursor cs, cf;
         cs.init(list_of(J, ws, seg, kListSpec), nspec);
         if (!fixup) cf.init(list_of(J, ws, seg, kListFix), nfix);
@@ -943,7 +987,29 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
             }
             return false;
         };
-        walk<RAM, INV>(J, C, R, a, e, emit, ws.err);
+        int32_t start = e;
+        int32_t stopped = 0;
+        if (arith) {
+            if (rec) {
+                for (int32_t c = start + C.w + 1; c <= b; c += C.w + 1) {
+                    start = c;
+                    if (emit(c)) {
+                        stopped = 1;
+                        break;
+                    }
+                }
+            }
+            if constexpr (Stage::kCoop) {   // the walker's outcome to the producer
+                if (rec && lane_id() == 0) {
+                    R.xfer[0] = start;
+                    R.xfer[1] = stopped;
+                }
+                __syncthreads();
+                start = (int32_t)uni((uint32_t)R.xfer[0]);
+                stopped = (int32_t)uni((uint32_t)R.xfer[1]);
+            }
+        }
+        if (!stopped) walk<RAM, INV>(J, C, R, a, start, emit, ws.err);
         if (!rec) return 0;
         wl.finish();
         new_nfix = min(wl.n, J.cap);

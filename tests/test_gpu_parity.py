@@ -158,6 +158,31 @@ def test_resolution_rounds(algo, seg):
         binding.set_tuning(0, 0)
 
 
+@pytest.mark.parametrize("w,M", [(1500, 9000), (4096, 65536), (1500, 1501),
+                                 (4096, 4097)])
+def test_constant_segments(w, M):
+    """RAM over runs that cover whole segments (resolved arithmetically:
+    every chunk inside such a run is w + 1 long), runs of different values
+    back to back, runs at the stream's ends, and max_chunk = w + 1 (fixed
+    size chunks whatever the bytes)."""
+    rng = np.random.default_rng(w + M)
+    x, _ = datagen.mixed_stream(16, 5)
+    parts = [np.full(300000, 0, np.uint8), x[:200000],
+             np.full(250000, 255, np.uint8), np.full(180000, 7, np.uint8),
+             x[200000:700000], np.full(400000, int(rng.integers(0, 256)), np.uint8),
+             x[700000:], np.full(123457, 3, np.uint8)]
+    x = np.concatenate(parts)
+    exp = oracle.chunk("ram", x, w, M)
+    try:
+        for seg, off in ((16384, 0), (65536, 5)):
+            binding.set_tuning(seg, 0)
+            say("case constant segments", w, M, seg, off)
+            got = gpu_cuts(x, "ram", w, M, off)
+            assert np.array_equal(got, exp), (w, M, seg, off)
+    finally:
+        binding.set_tuning(0, 0)
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("algo", ["ram", "ae", "maxp"])
 def test_mixed_1gib(algo):
