@@ -305,34 +305,67 @@ __device__ __forceinline__ void ae_start(Walker& W, const Ctx& C, int32_t c) {
     W.scan = 0;
 }
 
-// Window maximum under construction (RAM): whole tiles go into the
-// walker's T; in the window's first and last tiles every lane folds the
-// maximum of its bytes inside the window into acc (a partly covered lane
-// masks its bytes, so no lane-dependent branch is taken), and acc is reduced
-// once, where the window ends, unless T already is 255.
+// Window maximum under construction (RAM).  Whole tiles go into the
+// walker's T by their maxima; whole lanes of the window's first and last
+// tile go into acc by a select (reduced once, where the window ends).  A
+// partly covered lane is looked at only if it can matter: the one in the
+// window's first tile, when the window goes on past that tile, is kept in
+// scalar registers (its 16 bytes, byte range and lane maximum); those in the
+// tile where the window ends are read there.  At the window end nothing but
+// T is looked at when T already is 255, and a partial lane is reduced
+// exactly only when its lane maximum (an upper bound of its part) exceeds
+// the rest of the window.
 struct RamWin {
     uint32_t acc;                        // per lane
     int32_t used;
+    uint32_t q0, q1, q2, q3;             // kept lane's bytes
+    uint32_t kr;                         // 0, or first | end << 8 | lane max << 16 | 1 << 31
 
     __device__ __forceinline__ void reset() {
         acc = 0;
         used = 0;
+        kr = 0;
     }
-    // bytes [lo, hi) of the tile (offsets inside it, lo < hi)
-    __device__ __forceinline__ void add(const uint4& v, uint32_t lm, int32_t lo,
-                                        int32_t hi) {
-        const int32_t a = lo - 16 * (int32_t)lane_id(), b = hi - 16 * (int32_t)lane_id();
-        uint32_t m;
-        if ((lo | hi) & 15)              // some lane is covered in part
-            m = lane_max16(keep_bytes(v, a, b));
-        else
-            m = (a <= 0 && b >= 16) ? lm : 0u;
-        acc = max(acc, m);
-        used = 1;
+    // whole lanes among bytes [lo, hi) of the tile
+    __device__ __forceinline__ void whole(uint32_t lm, int32_t lo, int32_t hi) {
+        const int32_t fl = (lo + 15) >> 4, fh = hi >> 4;
+        if (fl < fh) {
+            const int32_t lane = (int32_t)lane_id();
+            acc = lane >= fl && lane < fh ? max(acc, lm) : acc;
+            used = 1;
+        }
     }
-    __device__ __forceinline__ uint32_t finish(uint32_t T) const {
-        if (T >= 255 || !used) return T;
-        return max(T, uni(wave_max(acc)));
+    // keep lane l's bytes [a, 16)
+    __device__ __forceinline__ void keep(const uint4& v, uint32_t lm, int32_t l,
+                                         int32_t a) {
+        q0 = (uint32_t)__builtin_amdgcn_readlane((int)v.x, l);
+        q1 = (uint32_t)__builtin_amdgcn_readlane((int)v.y, l);
+        q2 = (uint32_t)__builtin_amdgcn_readlane((int)v.z, l);
+        q3 = (uint32_t)__builtin_amdgcn_readlane((int)v.w, l);
+        const uint32_t ub = (uint32_t)__builtin_amdgcn_readlane((int)lm, l);
+        kr = (uint32_t)a | (16u << 8) | (ub << 16) | 0x80000000u;
+    }
+    // T at the window's end, which lies in the tile (v, lm) whose window
+    // bytes are [lo, hi) (offsets inside it)
+    __device__ __forceinline__ uint32_t finish(uint32_t T, const uint4& v,
+                                               uint32_t lm, int32_t lo,
+                                               int32_t hi) const {
+        if (T >= 255) return T;
+        if (used) T = max(T, uni(wave_max(acc)));
+        if (kr && ((kr >> 16) & 0xFFu) > T)
+            T = max(T, lane_range_max(Lane16{q0, q1, q2, q3}, (int)(kr & 15u), 16));
+        if (lo >= hi) return T;
+        const int32_t la = lo >> 4, lb = (hi - 1) >> 4;
+        if (lo & 15) {                   // partial first lane here
+            const int32_t e = la == lb ? ((hi - 1) & 15) + 1 : 16;
+            if ((uint32_t)__builtin_amdgcn_readlane((int)lm, la) > T)
+                T = max(T, lane_range_max(lane_words(v, la), lo & 15, e));
+        }
+        if ((hi & 15) && (la != lb || !(lo & 15))) {   // partial last lane here
+            if ((uint32_t)__builtin_amdgcn_readlane((int)lm, lb) > T)
+                T = max(T, lane_range_max(lane_words(v, lb), 0, hi & 15));
+        }
+        return T;
     }
 };
 
@@ -349,15 +382,24 @@ __device__ __forceinline__ bool ram_tile(Walker& W, RamWin& X, const Ctx& C,
         if (!W.scan) {
             // window bytes [cur, min(we, te)) of this tile
             const int32_t lo_t = W.cur - tp, hi_t = min(W.we, te) - tp;
-            if (lo_t == 0 && hi_t == kTile)
-                W.T = max(W.T, (int32_t)t.tmax);
-            else
-                X.add(v, lm, lo_t, hi_t);
-            if (W.we > te) {
+            if (W.we > te) {             // the window goes on
+                if (lo_t == 0) {
+                    W.T = max(W.T, (int32_t)t.tmax);
+                } else {
+                    X.whole(lm, lo_t, kTile);
+                    if (lo_t & 15) X.keep(v, lm, lo_t >> 4, lo_t & 15);
+                }
                 W.cur = te;
                 return false;
             }
-            W.T = (int32_t)X.finish((uint32_t)W.T);
+            int32_t flo = lo_t, fhi = hi_t;  // parts the finish reads
+            if (lo_t == 0 && hi_t == kTile) {
+                W.T = max(W.T, (int32_t)t.tmax);
+                flo = fhi = 0;
+            } else {
+                X.whole(lm, lo_t, hi_t);
+            }
+            W.T = (int32_t)X.finish((uint32_t)W.T, v, lm, flo, fhi);
             X.reset();
             W.scan = 1;
             W.cur = W.we;
@@ -427,6 +469,20 @@ __device__ __forceinline__ bool ae_tile(Walker& W, const Ctx& C, const Tile& t,
     const uint4 v = t.v();
     const uint32_t lm = t.lm();
     for (;;) {
+        if (W.T < 0 && C.w >= kTile) {
+            // The chunk's first byte is its first target, and every later
+            // record in this tile lies within the window of the one before
+            // it, so the target ends at the first maximum of the rest of
+            // the tile (up to the limit).
+            const int32_t hl = min(te, W.L);
+            int32_t q;
+            const uint32_t M = tile_range_argmax(t, v, lm, W.cur, hl, q);
+            W.we = q;
+            W.T = (int32_t)M + 1;
+            W.cur = hl;
+            if (W.cur >= te) return false;
+            continue;
+        }
         if (W.T < 0) {                   // the chunk's first byte
             const int32_t o = W.cur - tp;
             const uint32_t dw = (uint32_t)__builtin_amdgcn_readlane(
