@@ -158,7 +158,7 @@ const char* cdc_last_error(void);
  * Tuning knobs.  They change only speed, never the offsets.
  *   chain_segment    bytes per segment of the segment-parallel chain search
  *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 512 KiB);
- *   maxp_segment     bytes per MAXP work item (16 .. 2^28; 0: 64 KiB);
+ *   maxp_segment     bytes per MAXP work item (16 .. 2^28; 0: 256 KiB);
  *   waves_per_block  waves per workgroup of the MAXP and output passes (1 .. 4;
  *                    0: 4);
  *   reserved         must be 0.

@@ -43,7 +43,7 @@ constexpr uint64_t kMaxChunkLimit = 1ull << 28;
 // chain inside their segment; MAXP has no chain to rejoin (its candidates do
 // not depend on the chunk start) and splits finely for load balance.
 constexpr uint64_t kChainSegment = 512 << 10;
-constexpr uint64_t kMaxpSegment = 64 << 10;
+constexpr uint64_t kMaxpSegment = 256 << 10;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

@@ -62,6 +62,25 @@ __device__ void block_summaries(const uint4& v, int64_t tp, int64_t n,
     }
 }
 
+// Tiles [t0, t1) of a job, kAhead loads in flight per wave.
+template <int G>
+__device__ void block_tiles(const Source& src, int64_t t0, int64_t t1,
+                            int64_t n, uint8_t* bm, int64_t* bp) {
+    constexpr int kAhead = 4;
+    constexpr int64_t per_tile = kTile / (16 * G);   // blocks per tile
+    for (int64_t t = t0; t < t1; t += kAhead) {
+        uint4 v[kAhead];
+#pragma unroll
+        for (int i = 0; i < kAhead; i++)
+            v[i] = t + i < t1 ? src.load<false>(t + i) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < kAhead; i++)
+            if (t + i < t1)
+                block_summaries<G>(v[i], src.tile_pos(t + i), n, bm, bp,
+                                   (t + i) * per_tile);
+    }
+}
+
 __device__ void maxp_blocks_item(const JobView& J, uint32_t seg, uint8_t* bmax,
                                  int64_t* bpos) {
     Source src;
@@ -74,23 +93,16 @@ __device__ void maxp_blocks_item(const JobView& J, uint32_t seg, uint8_t* bmax,
     if (seg == 0) t0 = 0;
     const int64_t t1 = (b >= J.n) ? ((J.n + src.shift + kTile - 1) >> 10)
                                   : ((b + src.shift + kTile - 1) >> 10);
-    const int blog = (int)J.blog;
-    const int64_t per_tile = (int64_t)kTile >> blog;   // blocks per tile
     uint8_t* bm = bmax + J.blk0;
     int64_t* bp = bpos + J.blk0;
-    for (int64_t t = t0; t < t1; t++) {
-        const uint4 v = src.load<false>(t);
-        const int64_t tp = src.tile_pos(t);
-        const int64_t beta0 = t * per_tile;
-        switch (blog) {
-            case 4: block_summaries<1>(v, tp, J.n, bm, bp, beta0); break;
-            case 5: block_summaries<2>(v, tp, J.n, bm, bp, beta0); break;
-            case 6: block_summaries<4>(v, tp, J.n, bm, bp, beta0); break;
-            case 7: block_summaries<8>(v, tp, J.n, bm, bp, beta0); break;
-            case 8: block_summaries<16>(v, tp, J.n, bm, bp, beta0); break;
-            case 9: block_summaries<32>(v, tp, J.n, bm, bp, beta0); break;
-            default: block_summaries<64>(v, tp, J.n, bm, bp, beta0); break;
-        }
+    switch ((int)J.blog) {
+        case 4: block_tiles<1>(src, t0, t1, J.n, bm, bp); break;
+        case 5: block_tiles<2>(src, t0, t1, J.n, bm, bp); break;
+        case 6: block_tiles<4>(src, t0, t1, J.n, bm, bp); break;
+        case 7: block_tiles<8>(src, t0, t1, J.n, bm, bp); break;
+        case 8: block_tiles<16>(src, t0, t1, J.n, bm, bp); break;
+        case 9: block_tiles<32>(src, t0, t1, J.n, bm, bp); break;
+        default: block_tiles<64>(src, t0, t1, J.n, bm, bp); break;
     }
 }
 
