@@ -448,7 +448,9 @@ __device__ __forceinline__ bool ram_group(Walker& W, RamWin& X, const Ctx& C,
         if (W.cur == gp + i * kTile) {
             if (!W.scan) {
                 const int32_t kw = min(kSpan, (W.we - 1 - gp) >> 10);
-                for (; i < kw; i++) W.T = max(W.T, (int32_t)g.tmax(i));
+                if (W.T < 255)
+                    for (int32_t k = i; k < kw; k++) W.T = max(W.T, (int32_t)g.tmax(k));
+                i = max(i, kw);
             } else if (W.T > 0) {
                 const int32_t k = min(first_tile_ge(g.tmx, i, (uint32_t)W.T),
                                       (W.L - 1 - gp) >> 10);
