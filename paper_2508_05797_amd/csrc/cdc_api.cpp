@@ -429,6 +429,16 @@ void cdc_release(void) {
 }
 
 int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
+    return cdc::batch_run(jobs, n_jobs, 0, stream);
+}
+
+}  // extern "C"
+
+// A batch whose total length the caller knows (bytes_hint > 0) launches its
+// kernels with grids sized for that length; the kernels walk the planned
+// items grid-stride, so the grid only sets how many workgroups share them.
+int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
+                   hipStream_t stream) {
     t_last_error.clear();
     if (!jobs || n_jobs == 0) {
         t_last_error = "invalid argument";
@@ -475,7 +485,12 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
     P.jobs = jd;
     P.items = items;
     P.n_items = nitems;
-    const uint32_t grid_waves = (uint32_t)std::min<uint64_t>(caps.items, kMaxGridWaves);
+    uint64_t items_upper = caps.items;
+    if (bytes_hint > 0)
+        items_upper = std::min<uint64_t>(
+            items_upper, batch_caps(bytes_hint, n_jobs, 1, 2).items);
+    const uint32_t grid_waves = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(items_upper, kMaxGridWaves));
     ws.marks.level = g_profile_level;
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
     ChainWs cw;
@@ -493,6 +508,8 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
     if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
     return CDC_OK;
 }
+
+extern "C" {
 
 int cdc_chunk_each(cdc_job* host_jobs, uint32_t n_jobs, hipStream_t stream) {
     if (!host_jobs) return CDC_EINVAL;

@@ -128,4 +128,9 @@ hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 // stream must be idle).
 void drop_workspace(hipStream_t st);
 
+// cdc_chunk_batch with the batch's total length known to the caller (0: not
+// known); the length only sizes the launch grids.
+int batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
+              hipStream_t stream);
+
 }  // namespace cdc

@@ -81,11 +81,13 @@ public:
             j.max_chunk = q.max_chunk;
             j.status = 0;
         }
+        uint64_t total = 0;
+        for (size_t k = 0; k < batch.size(); k++) total += s.host[k].n;
         const size_t bytes = batch.size() * sizeof(cdc_job);
         if (hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice,
                            s.stream) != hipSuccess)
             return false;
-        if (cdc_chunk_batch(s.dev, (uint32_t)batch.size(), s.stream) != CDC_OK)
+        if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, s.stream) != CDC_OK)
             return false;
         if (hipMemcpyAsync(s.host, s.dev, bytes, hipMemcpyDeviceToHost,
                            s.stream) != hipSuccess ||

@@ -65,7 +65,7 @@ def test_host_only_entry_points():
     assert binding.get_tuning() == {"chain_segment": 4096, "maxp_segment": 65536,
                                     "waves_per_block": 2, "reserved": 0}
     assert L.cdc_set_tuning(None) == 0
-    assert binding.get_tuning() == {"chain_segment": 1 << 20, "maxp_segment": 1 << 16,
+    assert binding.get_tuning() == {"chain_segment": 1 << 19, "maxp_segment": 1 << 18,
                                     "waves_per_block": 4, "reserved": 0}
     assert L.cdc_autotune(None, 1, None, 1, None) == -1
     assert L.cdc_get_tuning(None) == -1
