@@ -273,6 +273,14 @@ def serve_leg(pool, binding, datagen, torch, np):
     del b
     out = {"batched_peak_gbs": round(peak / 1e9, 2), "budget_bytes": SERVE_BUDGET,
            "slots": SERVE_SLOTS, "max_batch": SERVE_MAX_BATCH, "loads": []}
+    # untimed warm-up of the serving path (first use of its streams and
+    # copies in this process), as the other legs' warm-up steps
+    rate = SERVE_LOADS[0] * peak / mean_size
+    offs, sizes, algos, wins = draw(4000, SERVE_SEED + 9)
+    reqs, total = binding.requests(offs, sizes, algos, wins, MAX_CHUNK,
+                                   np.cumsum(rng.exponential(1.0 / rate, 4000)))
+    binding.serve(pool, reqs, total, budget_bytes=SERVE_BUDGET,
+                  max_batch=SERVE_MAX_BATCH, slots=SERVE_SLOTS)
     for i, load in enumerate(SERVE_LOADS):
         rate = load * peak / mean_size
         k = max(100, int(rate * SERVE_SECONDS))

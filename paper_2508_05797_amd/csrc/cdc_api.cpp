@@ -86,6 +86,41 @@ struct EventMarks : Marks {
 
 int g_profile_level = 0;
 
+// Streams of a workspace for running the algorithms of a batch side by
+// side: AE, AE-Min and MAXP go to their own streams, forked from and joined
+// back into the caller's stream by events (under capture this becomes
+// parallel branches of the graph).  Default priority, non-blocking.
+struct SideStreams {
+    bool ok = false;
+    hipStream_t s[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+
+    bool create() {
+        for (int i = 0; i < 3; i++)
+            if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess)
+                return false;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+            return false;
+        ok = true;
+        return true;
+    }
+    void destroy() {
+        for (int i = 0; i < 3; i++) {
+            if (s[i]) {
+                (void)hipStreamSynchronize(s[i]);
+                (void)hipStreamDestroy(s[i]);
+            }
+            if (join[i]) (void)hipEventDestroy(join[i]);
+            s[i] = nullptr;
+            join[i] = nullptr;
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        fork = nullptr;
+        ok = false;
+    }
+};
+
 struct Workspace {
     EventMarks marks;
     void* dev = nullptr;
@@ -93,6 +128,7 @@ struct Workspace {
     // reservation for batches
     uint32_t res_jobs = 0;
     BatchCaps res_caps{};
+    SideStreams side;
 };
 
 std::mutex g_mu;
@@ -272,6 +308,7 @@ void drop_workspace(hipStream_t st) {
     auto it = g_ws.find({dev, (uintptr_t)st});
     if (it == g_ws.end()) return;
     if (it->second.dev) (void)hipFree(it->second.dev);
+    it->second.side.destroy();
     for (auto& r : it->second.marks.recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -422,6 +459,7 @@ void cdc_release(void) {
             (void)hipGetDevice(&cur);
             (void)hipSetDevice(kv.first.first);
             (void)hipFree(kv.second.dev);
+            kv.second.side.destroy();
             (void)hipSetDevice(cur);
         }
     }
@@ -429,7 +467,7 @@ void cdc_release(void) {
 }
 
 int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
-    return cdc::batch_run(jobs, n_jobs, 0, stream);
+    return cdc::batch_run(jobs, n_jobs, 0, true, stream);
 }
 
 }  // extern "C"
@@ -437,8 +475,10 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
 // A batch whose total length the caller knows (bytes_hint > 0) launches its
 // kernels with grids sized for that length; the kernels walk the planned
 // items grid-stride, so the grid only sets how many workgroups share them.
+// With side = false the algorithms run in order on `stream` (for callers
+// that overlap batches on streams of their own).
 int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-                   hipStream_t stream) {
+                   bool side, hipStream_t stream) {
     t_last_error.clear();
     if (!jobs || n_jobs == 0) {
         t_last_error = "invalid argument";
@@ -500,11 +540,35 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
     cw.rew = at<uint32_t>(ws.dev, L.rew);
     cw.err = at<uint32_t>(ws.dev, L.err);
     const int wpb = g_waves_per_block;
-    e = launch_ram_ae(P, grid_waves, n_jobs, nullptr, cw, wpb, stream, mk);
-    if (e == hipSuccess)
-        e = launch_maxp(P, grid_waves, n_jobs, nullptr, cw.meta, cw.spec,
-                        at<uint8_t>(ws.dev, L.bmax), at<int64_t>(ws.dev, L.bpos),
-                        cw.err, wpb, caps.blocks != 0, stream, mk);
+    // the algorithms of a batch are independent: side by side on their own
+    // streams (created on first use outside capture; until then in order)
+    SideStreams& sd = ws.side;
+    if (side && !sd.ok && !capturing(stream) && !sd.create()) sd.destroy();
+    auto maxp = [&](hipStream_t st) {
+        return launch_maxp(P, grid_waves, n_jobs, nullptr, cw.meta, cw.spec,
+                           at<uint8_t>(ws.dev, L.bmax), at<int64_t>(ws.dev, L.bpos),
+                           cw.err, wpb, caps.blocks != 0, st, mk);
+    };
+    if (side && sd.ok) {
+        e = hipEventRecord(sd.fork, stream);
+        for (int i = 0; i < 3 && e == hipSuccess; i++)
+            e = hipStreamWaitEvent(sd.s[i], sd.fork, 0);
+        if (e == hipSuccess)
+            e = launch_chain(P, kRam, grid_waves, n_jobs, nullptr, cw, stream, mk);
+        if (e == hipSuccess)
+            e = launch_chain(P, kAe, grid_waves, n_jobs, nullptr, cw, sd.s[0], mk);
+        if (e == hipSuccess)
+            e = launch_chain(P, kAeMin, grid_waves, n_jobs, nullptr, cw, sd.s[1], mk);
+        if (e == hipSuccess) e = maxp(sd.s[2]);
+        for (int i = 0; i < 3 && e == hipSuccess; i++) {
+            e = hipEventRecord(sd.join[i], sd.s[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, sd.join[i], 0);
+        }
+        if (e == hipSuccess) e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
+    } else {
+        e = launch_ram_ae(P, grid_waves, n_jobs, nullptr, cw, wpb, stream, mk);
+        if (e == hipSuccess) e = maxp(stream);
+    }
     if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
     return CDC_OK;
 }

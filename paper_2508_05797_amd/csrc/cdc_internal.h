@@ -113,6 +113,13 @@ hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int waves_per_block,
                          hipStream_t st, Marks* marks);
+// The passes of one algorithm (kRam, kAe or kAeMin), and the output copy of
+// all RAM / AE items (launch_ram_ae is the three and the copy in order).
+hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
+                        uint32_t jobs_upper, const uint32_t* n_jobs_d,
+                        const ChainWs& ws, hipStream_t st, Marks* marks);
+hipError_t launch_emit(const Plan& P, uint32_t items_upper, const ChainWs& ws,
+                       int waves_per_block, hipStream_t st, Marks* marks);
 hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                        const uint32_t* n_jobs_d, SegMeta* meta,
                        uint32_t* cand, uint8_t* bmax, int64_t* bpos,
@@ -129,8 +136,10 @@ hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 void drop_workspace(hipStream_t st);
 
 // cdc_chunk_batch with the batch's total length known to the caller (0: not
-// known); the length only sizes the launch grids.
+// known; the length only sizes the launch grids), and the choice of running
+// the algorithms side by side on the workspace's own streams (side) or in
+// order on `stream`.
 int batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-              hipStream_t stream);
+              bool side, hipStream_t stream);
 
 }  // namespace cdc

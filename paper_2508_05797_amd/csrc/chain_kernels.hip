@@ -1328,23 +1328,42 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
                n_jobs_d, ws);
 }
 
+hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
+                        uint32_t jobs_upper, const uint32_t* n_jobs_d,
+                        const ChainWs& ws, hipStream_t st, Marks* mk) {
+    const bool one = P.jobs == nullptr;
+    if (algo == kRam)
+        launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
+                                 st, mk, one ? "speculate_ram" : "speculate_batch_ram");
+    else if (algo == kAe)
+        launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
+                                  st, mk, one ? "speculate_ae" : "speculate_batch_ae");
+    else
+        launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
+                                 st, mk, one ? "speculate_ae_min" : "speculate_batch_ae_min");
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const Plan& P, uint32_t items_upper, const ChainWs& ws,
+                       int wpb, hipStream_t st, Marks* mk) {
+    const dim3 blk(kWave * wpb), grid((items_upper + wpb - 1) / wpb);
+    CDC_LAUNCH(mk, 2, "emit", k_emit, grid, blk, 0, st, P, ws);
+    return hipGetLastError();
+}
+
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int wpb, hipStream_t st,
                          Marks* mk) {
     const bool one = P.jobs == nullptr;
-    if (!one || P.one.algo == kRam)
-        launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, wpb,
-                                 st, mk, one ? "speculate_ram" : "speculate_batch_ram");
-    if (!one || P.one.algo == kAe)
-        launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, wpb,
-                                  st, mk, one ? "speculate_ae" : "speculate_batch_ae");
-    if (!one || P.one.algo == kAeMin)
-        launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, wpb,
-                                 st, mk, one ? "speculate_ae_min" : "speculate_batch_ae_min");
-    const dim3 blk(kWave * wpb), grid((items_upper + wpb - 1) / wpb);
-    CDC_LAUNCH(mk, 2, "emit", k_emit, grid, blk, 0, st, P, ws);
-    return hipGetLastError();
+    for (uint32_t algo : {kRam, kAe, kAeMin}) {
+        if (!one || P.one.algo == algo) {
+            const hipError_t e = launch_chain(P, algo, items_upper, jobs_upper,
+                                              n_jobs_d, ws, st, mk);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return launch_emit(P, items_upper, ws, wpb, st, mk);
 }
 
 }  // namespace cdc

@@ -87,7 +87,8 @@ public:
         if (hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice,
                            s.stream) != hipSuccess)
             return false;
-        if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, s.stream) != CDC_OK)
+        // batches overlap across slots; within one, the algorithms run in order
+        if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, false, s.stream) != CDC_OK)
             return false;
         if (hipMemcpyAsync(s.host, s.dev, bytes, hipMemcpyDeviceToHost,
                            s.stream) != hipSuccess ||
