@@ -109,10 +109,14 @@ def test_batch_rejects_invalid_jobs():
             assert np.array_equal(b.result(j).cpu().numpy().astype(np.uint64), exp)
 
 
-def test_batch_graph_replay():
+@pytest.mark.parametrize("eager_first", [False, True])
+def test_batch_graph_replay(eager_first):
     """Capture one batched call per algorithm into a HIP graph after a
     reservation, replay it several times with eager work in between, and
-    check every replay; then change the descriptors' data and replay."""
+    check every replay; then change the descriptors' data and replay.  With
+    an eager call first, the batch's side streams exist when the capture
+    starts, so the graph holds the algorithms as parallel branches (forked
+    and joined by events); without, the capture runs them in order."""
     host, offs, sizes = make_files(200, 31)
     d = torch.from_numpy(host).cuda()
     s = torch.cuda.Stream()
@@ -120,6 +124,9 @@ def test_batch_graph_replay():
         binding.reserve(int(sizes.sum()) + (1 << 20), 256, 2048, 65536, stream=s)
         bs = [binding.Batch(d, offs, sizes, a, ALGO_W[a], 65536)
               for a in ("ram", "ae", "maxp")]
+        if eager_first:
+            for b in bs:
+                b.run(stream=s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
