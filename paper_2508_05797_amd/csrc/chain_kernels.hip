@@ -1,22 +1,25 @@
 // RAM and AE chunk chains on gfx950: speculate, fix up, resolve, emit.
 //
-// The two patterns of the paper (Section 4) as wavefront operations on a
-// 1 KiB tile (64 lanes x 16 B) staged through a per-wave LDS ring:
-//   * extreme byte search (Section 4.1): each lane keeps a running maximum of
-//     its 16-byte pieces of the window (SWAR v_pk_max_u16); the 64 lane
-//     maxima are reduced (DPP) once, where the window ends; the at most two
-//     lanes that the window covers only in part are read out (readlane) and
-//     reduced on uniform values;
-//   * range scan (Section 4.2): a ballot of "lane maximum >= T" names the
-//     lanes that can hold a hit; the first one is read out and its bytes are
-//     compared with T as four SWAR words.
+// The two patterns of the paper (Section 4) as wavefront operations on
+// 1 KiB tiles (64 lanes x 16 B).  A producer wave stages tiles with their
+// lane maxima (SWAR v_pk_max_u16) and tile maxima (DPP) into LDS; a walker
+// wave runs the chain over them:
+//   * extreme byte search (Section 4.1): a window's maximum comes from the
+//     maxima of the tiles it covers whole, plus the lanes of its first and
+//     last tile (whole lanes by a per-lane select, reduced once by DPP where
+//     the window ends; partly covered lanes read out only when they can
+//     still raise the maximum);
+//   * range scan (Section 4.2): tiles whose maximum is below the threshold
+//     are passed by one SWAR compare of the packed tile maxima; in the tile
+//     that can hold a hit, a ballot of "lane maximum >= T" names the lanes,
+//     and the first one's bytes are compared with T as SWAR words.
 // RAM (Section 2.1 "RAM"; Section 4.3) is one window maximum followed by a
 // greater-or-equal scan; AE-Max (Section 2.1 "AE"; Section 4.3) is a chain of
-// greater-than scans from the current target, which reads every byte once
-// (AE-Min runs as AE-Max of the complemented bytes).  A walker's state
-// (chunk start, limit, position, threshold) is uniform and lives in scalar
-// registers; per tile it costs the lane maxima and a few scalar compares
-// unless a chunk boundary falls into the tile.
+// greater-than scans from the current target (inside one tile, and for
+// windows of at least a tile, the chain's targets collapse to the first
+// maximum of the rest of the tile); AE-Min runs as AE-Max of the
+// complemented bytes.  A walker's state (chunk start, limit, position,
+// threshold) is uniform and lives in scalar registers.
 //
 // The chain (cut k+1 depends on cut k) is split into segments.  Speculation
 // runs one walker per segment from the segment start and records its cuts up
@@ -26,7 +29,9 @@
 // segment whose fix-up never lands hands its successor an entry that the
 // fix-up did not assume; parallel rounds re-walk exactly those successors
 // (landing on either recorded list), and an ordered pass per job settles
-// what is left.  The emit pass copies every segment's resolved pieces.
+// what is left.  RAM segments of a single byte value are resolved
+// arithmetically (RAM chains there never meet).  The emit pass copies every
+// segment's resolved pieces.
 #include "wave.h"
 
 namespace cdc {
@@ -1316,9 +1321,8 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
 template <bool RAM, bool INV>
 static void launch_algo(const Plan& P, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
-                        const ChainWs& ws, int wpb, hipStream_t st, Marks* mk,
+                        const ChainWs& ws, hipStream_t st, Marks* mk,
                         const char* spec_name) {
-    (void)wpb;
     if (P.jobs == nullptr)
         launch_passes<RAM, INV, true>(P, items_upper, ws, st, mk, spec_name);
     else
@@ -1333,14 +1337,14 @@ hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
                         const ChainWs& ws, hipStream_t st, Marks* mk) {
     const bool one = P.jobs == nullptr;
     if (algo == kRam)
-        launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
-                                 st, mk, one ? "speculate_ram" : "speculate_batch_ram");
+        launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
+                                 mk, one ? "speculate_ram" : "speculate_batch_ram");
     else if (algo == kAe)
-        launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
-                                  st, mk, one ? "speculate_ae" : "speculate_batch_ae");
+        launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
+                                  mk, one ? "speculate_ae" : "speculate_batch_ae");
     else
-        launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, 0,
-                                 st, mk, one ? "speculate_ae_min" : "speculate_batch_ae_min");
+        launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
+                                 mk, one ? "speculate_ae_min" : "speculate_batch_ae_min");
     return hipGetLastError();
 }
 
