@@ -54,7 +54,7 @@ SERVE_LOADS = (0.25, 0.5, 0.9)
 SERVE_SECONDS = 0.5            # arrivals per load level
 SERVE_BUDGET = 32 << 30        # HBM for requests in flight
 SERVE_SLOTS = 4
-SERVE_MAX_BATCH = 4096
+SERVE_MAX_BATCH = 16384
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_2508_05797_amd", "csrc")
 
