@@ -263,7 +263,7 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
 }
 
 struct BatchLayout {
-    size_t err, nitems, jd, items, meta, spec, fix, rew, bpos, bmax, total;
+    size_t err, nitems, bsum, jd, items, meta, spec, fix, rew, bpos, bmax, total;
 };
 
 BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
@@ -271,6 +271,7 @@ BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
     size_t off = 0;
     L.err = off;    off += 256;
     L.nitems = off; off += 256;
+    L.bsum = off;   off = align_up(off + plan_bsum_bytes(n_jobs), 256);
     L.jd = off;     off = align_up(off + n_jobs * sizeof(JobDesc), 256);
     L.items = off;  off = align_up(off + c.items * sizeof(Item), 256);
     L.meta = off;   off = align_up(off + c.items * sizeof(SegMeta), 256);
@@ -519,7 +520,7 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
     Item* items = at<Item>(ws.dev, L.items);
     uint32_t* nitems = at<uint32_t>(ws.dev, L.nitems);
     hipError_t e = launch_plan(const_cast<cdc_job*>(jobs), n_jobs, caps, jd,
-                               items, nitems, stream);
+                               items, nitems, at<uint8_t>(ws.dev, L.bsum), stream);
     if (e != hipSuccess) { set_error("plan launch", e); return CDC_EHIP; }
     Plan P{};
     P.jobs = jd;

@@ -126,9 +126,14 @@ hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                        uint32_t* err, int waves_per_block, bool any_blocks,
                        hipStream_t st, Marks* marks);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st);
+// Batch planning: ctl[0] receives the item count, ctl[1] the overflow flag;
+// bsum holds plan_blocks(n_jobs) block totals.
 hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
-                       JobDesc* jd, Item* items, uint32_t* n_items,
+                       JobDesc* jd, Item* items, uint32_t* ctl, void* bsum,
                        hipStream_t st);
+constexpr size_t plan_bsum_bytes(uint64_t n_jobs) {
+    return (size_t)((n_jobs + 1023) / 1024) * 24;
+}
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 
 // Free the workspace of a stream the caller is about to destroy (the
