@@ -173,28 +173,28 @@ def batch_leg(binding, datagen, torch, np):
     del host
     stream = torch.cuda.Stream()
     out = {"files": N_FILES, "bytes": total}
+    # every file under every algorithm: one job table of 3 x 20,000 jobs, so
+    # one batched call runs the three algorithms side by side
+    k = len(ALGOS)
+    job_offs = np.tile(offs[:-1], k)
+    job_sizes = np.tile(sizes, k)
+    job_algos = [a for a, _w in ALGOS for _ in range(N_FILES)]
+    job_wins = np.repeat([w for _a, w in ALGOS], N_FILES)
     with torch.cuda.stream(stream):
-        batches = {a: binding.Batch(d, offs[:-1], sizes, a, w, MAX_CHUNK)
-                   for a, w in ALGOS}
+        b = binding.Batch(d, job_offs, job_sizes, job_algos, job_wins, MAX_CHUNK)
         torch.cuda.synchronize()
-        tunings = {}
-        for a, _w in ALGOS:
-            t0 = time.perf_counter()
-            tunings[a] = binding.autotune(batches[a], reps=2, stream=stream)
-            log("batch: autotune %s -> %s (%.1f s)" % (a, tunings[a],
-                                                      time.perf_counter() - t0))
-        out["tuning"] = binding.get_tuning()
-        # reserve for the largest batch, then capture one call per algorithm
-        binding.reserve(total, N_FILES, min(w for _, w in ALGOS), MAX_CHUNK,
-                        stream=stream)
-        for b in batches.values():
-            b.cuts.fill_(-1)
-            b.n_cuts.fill_(-1)
+        t0 = time.perf_counter()
+        out["tuning"] = binding.autotune(b, reps=2, stream=stream)
+        log("batch: autotune -> %s (%.1f s)" % (out["tuning"], time.perf_counter() - t0))
+        # reserve for the batch, then capture one batched call
+        binding.reserve(k * total, k * N_FILES, min(w for _, w in ALGOS),
+                        MAX_CHUNK, stream=stream)
+        b.cuts.fill_(-1)
+        b.n_cuts.fill_(-1)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            for a, _w in ALGOS:
-                batches[a].run(stream=stream)
+            b.run(stream=stream)
         # replays run on the capture stream, timed with events on it
         g.replay()
         torch.cuda.synchronize()
@@ -206,39 +206,35 @@ def batch_leg(binding, datagen, torch, np):
         e1.record(stream)
         torch.cuda.synchronize()
     ms_batched = e0.elapsed_time(e1) / reps
-    st = {a: b.statuses() for a, b in batches.items()}
-    assert all((s == 0).all() for s in st.values()), "batch job failed"
-    batched_nc = {a: b.n_cuts.clone() for a, b in batches.items()}
-    batched_cuts = {a: b.cuts.clone() for a, b in batches.items()}
+    assert (b.statuses() == 0).all(), "batch job failed"
+    batched_nc = b.n_cuts.clone()
+    batched_cuts = b.cuts.clone()
 
-    # plain: one cdc_chunk per file, per algorithm, on one stream
+    # plain: one cdc_chunk per file and algorithm, on one stream
     with torch.cuda.stream(stream):
-        for b in batches.values():
-            b.cuts.fill_(-1)
-            b.n_cuts.fill_(-1)
-            b.run_each(stream=stream)         # warm-up
+        b.cuts.fill_(-1)
+        b.n_cuts.fill_(-1)
+        b.run_each(stream=stream)             # warm-up
         torch.cuda.synchronize()
         e0, e1 = events()
         e0.record(stream)
-        for b in batches.values():
-            b.run_each(stream=stream)
+        b.run_each(stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1)
-    same = all(torch.equal(batched_nc[a], batches[a].n_cuts) and
-               torch.equal(batched_cuts[a], batches[a].cuts)
-               for a in batches)
+    same = torch.equal(batched_nc, b.n_cuts) and torch.equal(batched_cuts, b.cuts)
     steps_bytes = len(ALGOS) * total
     out.update({
         "batched_gbs": round(steps_bytes / (ms_batched * 1e-3) / 1e9, 2),
         "plain_gbs": round(steps_bytes / (ms_plain * 1e-3) / 1e9, 2),
         "batched_ms": round(ms_batched, 3), "plain_ms": round(ms_plain, 3),
         "batched_identical_to_plain": bool(same),
-        "n_cuts": {a: int(batched_nc[a].sum().item()) for a in batches},
+        "n_cuts": {a: int(batched_nc[i * N_FILES:(i + 1) * N_FILES].sum().item())
+                   for i, (a, _w) in enumerate(ALGOS)},
     })
     out["speedup"] = round(out["batched_gbs"] / out["plain_gbs"], 2)
     log("batch:", out)
-    del g, batches
+    del g, b
     return d, sizes, out
 
 

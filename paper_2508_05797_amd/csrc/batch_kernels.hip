@@ -22,14 +22,27 @@ __device__ __forceinline__ uint32_t blog_for(uint32_t w) {
     return lg >= 4 ? lg : 0;
 }
 
-// Three counts per job (work items, cut slots, MAXP blocks), scanned
-// together.
+// Counts per job, scanned together: work items per algorithm (so that each
+// algorithm's items are contiguous), cut slots, MAXP blocks.
+constexpr int kNumCounts = 6;
+constexpr int kSlots = 4, kBlocks = 5;
+
 struct Counts {
-    uint64_t items, slots, blocks;
+    uint64_t v[kNumCounts];
 };
 
+__device__ __forceinline__ Counts zero_counts() {
+    Counts c;
+#pragma unroll
+    for (int i = 0; i < kNumCounts; i++) c.v[i] = 0;
+    return c;
+}
+
 __device__ __forceinline__ Counts add(const Counts& x, const Counts& y) {
-    return Counts{x.items + y.items, x.slots + y.slots, x.blocks + y.blocks};
+    Counts c;
+#pragma unroll
+    for (int i = 0; i < kNumCounts; i++) c.v[i] = x.v[i] + y.v[i];
+    return c;
 }
 
 __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int o) {
@@ -44,28 +57,31 @@ __device__ Counts plan_exscan(const Counts& v, Counts* wsum, Counts& total) {
     const uint32_t nw = blockDim.x / kWave;
     Counts inc = v;
     for (int o = 1; o < kWave; o <<= 1) {
-        const Counts u{shfl_up64(inc.items, o), shfl_up64(inc.slots, o),
-                       shfl_up64(inc.blocks, o)};
+        Counts u;
+#pragma unroll
+        for (int i = 0; i < kNumCounts; i++) u.v[i] = shfl_up64(inc.v[i], o);
         if ((int)lane >= o) inc = add(inc, u);
     }
     if (lane == kWave - 1) wsum[wave] = inc;
     __syncthreads();
-    Counts pre{0, 0, 0}, tot{0, 0, 0};
+    Counts pre = zero_counts(), tot = zero_counts();
     for (uint32_t k = 0; k < nw; k++) {
         if (k < wave) pre = add(pre, wsum[k]);
         tot = add(tot, wsum[k]);
     }
     __syncthreads();                     // wsum is reused by the next call
     total = tot;
-    return Counts{pre.items + inc.items - v.items, pre.slots + inc.slots - v.slots,
-                  pre.blocks + inc.blocks - v.blocks};
+    Counts ex;
+#pragma unroll
+    for (int i = 0; i < kNumCounts; i++) ex.v[i] = pre.v[i] + inc.v[i] - v.v[i];
+    return ex;
 }
 
 // One job's descriptor (without its offsets) and its counts.
 __device__ JobDesc plan_job(cdc_job* jobs, uint32_t j, const BatchCaps& caps,
                             Counts& c) {
     JobDesc d{};
-    c = Counts{0, 0, 0};
+    c = zero_counts();
     const cdc_job q = jobs[j];
     const bool ok = q.algo <= 3 && q.window >= 1 &&
                     (uint64_t)q.max_chunk >= (uint64_t)q.window + 1 &&
@@ -90,14 +106,14 @@ __device__ JobDesc plan_job(cdc_job* jobs, uint32_t j, const BatchCaps& caps,
         // a job's chains never hold more cuts than the job has
         cap = min(cap, (q.n + kTile) / ((uint64_t)q.window + 1) + 2);
         d.cap = (uint32_t)cap;
-        c.slots = nseg * cap;
+        c.v[kSlots] = nseg * cap;
         d.blog = maxp ? blog_for(q.window) : 0;
         if (maxp && d.blog) {
             const uint64_t shift = (uintptr_t)q.data & 15;
-            c.blocks = (q.n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> d.blog);
+            c.v[kBlocks] = (q.n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> d.blog);
         }
+        c.v[q.algo] = nseg;
     }
-    c.items = nseg;
     d.nseg = (uint32_t)nseg;
     return d;
 }
@@ -111,39 +127,48 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
     cdc_job* jobs, uint32_t n_jobs, BatchCaps caps, JobDesc* jd, Counts* bsum) {
     __shared__ Counts wsum[kPlanThreads / kWave];
     const uint32_t j = blockIdx.x * kPlanThreads + threadIdx.x;
-    Counts c{0, 0, 0};
+    Counts c = zero_counts();
     JobDesc d{};
     if (j < n_jobs) d = plan_job(jobs, j, caps, c);
     Counts t;
     const Counts e = plan_exscan(c, wsum, t);
     if (j < n_jobs) {
-        d.item0 = (uint32_t)e.items;
-        d.slot0 = e.slots;
-        d.blk0 = e.blocks;
+        d.item0 = d.ok ? (uint32_t)e.v[d.algo] : 0u;
+        d.slot0 = e.v[kSlots];
+        d.blk0 = e.v[kBlocks];
         jd[j] = d;
     }
     if (threadIdx.x == 0) bsum[blockIdx.x] = t;
 }
 
-// (2) One block turns the block totals into block offsets and checks the
-// totals against the workspace capacity (ctl[0] = items, ctl[1] = overflow).
+// (2) One block turns the block totals into block offsets, places each
+// algorithm's items after the previous algorithm's, and checks the totals
+// against the workspace capacity.  ctl: [0] items, [1] overflow flag,
+// [2 + a] and [6 + a] the first and end item of algorithm a.
 __global__ __launch_bounds__(kPlanThreads) void k_plan_scan(
     uint32_t n_blocks, BatchCaps caps, Counts* bsum, uint32_t* ctl) {
     __shared__ Counts wsum[kPlanThreads / kWave];
-    Counts carry{0, 0, 0};
+    Counts carry = zero_counts();
     for (uint32_t base = 0; base < n_blocks; base += kPlanThreads) {
         const uint32_t k = base + threadIdx.x;
-        const Counts v = k < n_blocks ? bsum[k] : Counts{0, 0, 0};
+        const Counts v = k < n_blocks ? bsum[k] : zero_counts();
         Counts t;
         const Counts e = plan_exscan(v, wsum, t);
         if (k < n_blocks) bsum[k] = add(carry, e);
         carry = add(carry, t);
     }
     if (threadIdx.x == 0) {
-        const bool over = carry.items > caps.items || carry.slots > caps.slots ||
-                          carry.blocks > caps.blocks;
+        const uint64_t items = carry.v[0] + carry.v[1] + carry.v[2] + carry.v[3];
+        const bool over = items > caps.items || carry.v[kSlots] > caps.slots ||
+                          carry.v[kBlocks] > caps.blocks;
         ctl[1] = over ? 1u : 0u;
-        ctl[0] = over ? 0u : (uint32_t)carry.items;
+        ctl[0] = over ? 0u : (uint32_t)items;
+        uint64_t first = 0;
+        for (int a = 0; a < 4; a++) {
+            ctl[2 + a] = over ? 0u : (uint32_t)first;
+            first += carry.v[a];
+            ctl[6 + a] = over ? 0u : (uint32_t)first;
+        }
     }
 }
 
@@ -158,9 +183,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_items(
     JobDesc d = jd[j];
     const Counts o = bsum[blockIdx.x];
     const bool valid = d.ok != 0;
-    d.item0 += (uint32_t)o.items;
-    d.slot0 += o.slots;
-    d.blk0 += o.blocks;
+    if (valid) d.item0 += ctl[2 + d.algo] + (uint32_t)o.v[d.algo];
+    d.slot0 += o.v[kSlots];
+    d.blk0 += o.v[kBlocks];
     if (over) d.ok = 0;
     jd[j] = d;
     jobs[j].status = over ? CDC_ENOMEM : (valid ? CDC_OK : CDC_EINVAL);

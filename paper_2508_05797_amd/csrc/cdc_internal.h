@@ -75,7 +75,7 @@ struct Item {
 struct Plan {
     const JobDesc* jobs;     // device job table, or nullptr for one job
     const Item* items;       // device item table (with jobs)
-    const uint32_t* n_items; // device item count (with jobs)
+    const uint32_t* n_items; // device item count and per-algorithm item ranges (with jobs)
     JobDesc one;             // the single job (jobs == nullptr)
     uint32_t one_items;      // its item count
 };
@@ -126,13 +126,14 @@ hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                        uint32_t* err, int waves_per_block, bool any_blocks,
                        hipStream_t st, Marks* marks);
 hipError_t launch_set_u64(uint64_t* p, uint64_t v, hipStream_t st);
-// Batch planning: ctl[0] receives the item count, ctl[1] the overflow flag;
-// bsum holds plan_blocks(n_jobs) block totals.
+// Batch planning: ctl[0] receives the item count, ctl[1] the overflow flag,
+// ctl[2 + a] / ctl[6 + a] the first / end item of algorithm a (each
+// algorithm's items are contiguous); bsum holds the per-block totals.
 hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
                        JobDesc* jd, Item* items, uint32_t* ctl, void* bsum,
                        hipStream_t st);
 constexpr size_t plan_bsum_bytes(uint64_t n_jobs) {
-    return (size_t)((n_jobs + 1023) / 1024) * 24;
+    return (size_t)((n_jobs + 1023) / 1024) * 48;
 }
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 

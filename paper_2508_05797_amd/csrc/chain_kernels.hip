@@ -1095,7 +1095,8 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
 
 // The per-item kernels run one workgroup of two waves (producer and walker)
 // per item: with one job the grid covers its segments (one each); with a
-// job table the workgroups walk the item table grid-stride.
+// job table the workgroups walk the algorithm's range of the item table
+// grid-stride.
 constexpr int kCoopThreads = 2 * kWave;
 
 template <bool ONE, class F>
@@ -1106,7 +1107,9 @@ __device__ __forceinline__ void for_items(const Plan& P, uint32_t want, F&& f) {
         const JobView J = view(P.one);
         if (J.ok && J.algo == want) f(J, wid, wid);
     } else {
-        for (uint32_t wid = uni(blockIdx.x); wid < uni(*P.n_items); wid += gridDim.x) {
+        uint32_t first, last;
+        item_range(P, want, first, last);
+        for (uint32_t wid = first + uni(blockIdx.x); wid < last; wid += gridDim.x) {
             const Item it = P.items[wid];
             const JobView J = view(P.jobs[uni(it.job)]);
             if (J.ok && J.algo == want) f(J, uni(it.seg), wid);

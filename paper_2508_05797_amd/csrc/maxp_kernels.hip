@@ -109,8 +109,9 @@ __device__ void maxp_blocks_item(const JobView& J, uint32_t seg, uint8_t* bmax,
 __global__ __launch_bounds__(256) void k_maxp_blocks(Plan P, uint8_t* bmax,
                                                      int64_t* bpos,
                                                      uint32_t* err) {
-    const uint32_t count = item_count(P);
-    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+    uint32_t first, last;
+    item_range(P, kMaxp, first, last);
+    for (uint32_t wid = first + wave_global_id(); wid < last; wid += wave_count()) {
         JobView J;
         uint32_t seg;
         if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp ||
@@ -226,8 +227,9 @@ __global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax
                                                      SegMeta* meta,
                                                      uint32_t* cand,
                                                      uint32_t* err) {
-    const uint32_t count = item_count(P);
-    for (uint32_t wid = wave_global_id(); wid < count; wid += wave_count()) {
+    uint32_t first, last;
+    item_range(P, kMaxp, first, last);
+    for (uint32_t wid = first + wave_global_id(); wid < last; wid += wave_count()) {
         JobView J;
         uint32_t seg;
         if (!item_of(P, wid, J, seg) || !J.ok || J.algo != kMaxp) continue;

@@ -205,6 +205,19 @@ __device__ __forceinline__ uint32_t item_count(const Plan& P) {
     return P.jobs == nullptr ? P.one_items : uni(*P.n_items);
 }
 
+// Items [first, last) of algorithm `algo` (with one job: all of its items if
+// it runs that algorithm).
+__device__ __forceinline__ void item_range(const Plan& P, uint32_t algo,
+                                           uint32_t& first, uint32_t& last) {
+    if (P.jobs == nullptr) {
+        first = 0;
+        last = P.one.algo == algo ? P.one_items : 0u;
+    } else {
+        first = uni(P.n_items[2 + algo]);
+        last = uni(P.n_items[6 + algo]);
+    }
+}
+
 __device__ __forceinline__ bool item_of(const Plan& P, uint32_t wid,
                                         JobView& J, uint32_t& seg) {
     if (P.jobs == nullptr) {
