@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstring>
 #include <vector>
 
 #include "cdc.h"
@@ -40,6 +41,7 @@ public:
             if (s.host) (void)hipHostFree(s.host);
             if (s.stream) (void)hipStreamDestroy(s.stream);
         }
+        if (scratch_) (void)hipFree(scratch_);
     }
 
     int setup(uint32_t n_slots, uint32_t max_batch, uint64_t budget,
@@ -55,6 +57,26 @@ public:
             const int rc = cdc_reserve(s.stream, budget, max_batch, min_window,
                                        max_chunk);
             if (rc != CDC_OK) return rc;
+            // touch the pinned descriptors now, not while serving
+            memset(s.host, 0, max_batch * sizeof(cdc_job));
+        }
+        // one empty batch per slot, so that no request pays for the first
+        // use of a stream and its launches
+        if (hipMalloc(&scratch_, 2 * sizeof(uint64_t)) != hipSuccess) return CDC_EHIP;
+        for (Slot& s : slots_) {
+            cdc_job& j = s.host[0];
+            j.data = pool_;
+            j.n = 0;
+            j.cut_offsets = (uint64_t*)scratch_;
+            j.n_cuts = (uint64_t*)scratch_ + 1;
+            j.algo = CDC_RAM;
+            j.window = min_window;
+            j.max_chunk = max_chunk;
+            j.status = 0;
+            if (hipMemcpyAsync(s.dev, s.host, sizeof(cdc_job), hipMemcpyHostToDevice,
+                               s.stream) != hipSuccess ||
+                cdc::batch_run(s.dev, 1, 0, false, s.stream) != CDC_OK)
+                return CDC_EHIP;
         }
         for (Slot& s : slots_)
             if (hipStreamSynchronize(s.stream) != hipSuccess) return CDC_EHIP;
@@ -136,6 +158,7 @@ private:
     int32_t* status_;
     std::vector<Slot> slots_;
     std::chrono::steady_clock::time_point t0_;
+    void* scratch_ = nullptr;            // outputs of the warm-up batches
     bool error_ = false;
 };
 
