@@ -82,6 +82,37 @@ def test_batch_equals_plain(algo):
     check_batch(b1, host, offs, sizes, [algo] * 120, [w] * 120, [65536] * 120)
 
 
+def test_batch_many_jobs():
+    """More jobs than one planning block holds (2,600, so three blocks), the
+    four algorithms interleaved, and invalid jobs among them: every valid
+    job equals the oracle and each algorithm's items stay its own."""
+    host, offs, sizes = make_files(2600, 41, max_len=256 << 10)
+    rng = np.random.default_rng(43)
+    algos = [["ram", "ae", "maxp", "ae_min"][i] for i in rng.integers(0, 4, 2600)]
+    windows = np.array([ALGO_W[a] for a in algos], np.uint32)
+    bad = rng.choice(np.arange(3, 2600), 25, replace=False)
+    windows[bad] = 0                     # rejected by the planner
+    d = torch.from_numpy(host).cuda()
+    b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+    say("case batch many jobs", b.n_jobs, b.total_bytes)
+    b.run()
+    torch.cuda.synchronize()
+    nc = b.n_cuts.cpu().numpy()
+    cuts = b.cuts.cpu().numpy()
+    st = b.statuses()
+    bad_set = set(int(j) for j in bad)
+    for j in range(2600):
+        if j in bad_set:
+            assert st[j] == -1 and nc[j] == 0, (j, st[j], nc[j])   # CDC_EINVAL
+            continue
+        assert st[j] == 0, (j, st[j])
+        x = host[offs[j]:offs[j] + sizes[j]]
+        exp = oracle.chunk(algos[j], x, int(windows[j]), 65536)
+        got = cuts[int(b.cut_base[j]):int(b.cut_base[j]) + int(nc[j])]
+        assert np.array_equal(got.astype(np.uint64), exp), (j, algos[j], sizes[j])
+    assert binding.device_errors() == 0
+
+
 def test_batch_rejects_invalid_jobs():
     host, offs, sizes = make_files(40, 21)
     d = torch.from_numpy(host).cuda()
