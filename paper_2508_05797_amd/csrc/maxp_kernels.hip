@@ -125,10 +125,17 @@ __device__ __forceinline__ uint32_t byte_at(const uint8_t* d, int64_t p) {
     return d[p];
 }
 
-// Exact check that every byte in [lo, hi] is below v.
+// Exact check that every byte in [lo, hi] (job positions) is below v,
+// 1 <= v <= 255: 16 bytes per load, from the 16-byte granules that hold the
+// range (as the tile loads do), bytes outside the range masked to zero.
 __device__ bool all_below(const uint8_t* d, int64_t lo, int64_t hi, uint32_t v) {
-    for (int64_t p = lo; p <= hi; p++)
-        if (byte_at(d, p) >= v) return false;
+    const uintptr_t a = (uintptr_t)(d + lo), b = (uintptr_t)(d + hi);
+    for (uintptr_t g = a & ~(uintptr_t)15; g <= b; g += 16) {
+        const uint4 q = *(const uint4*)g;
+        const int ka = a > g ? (int)(a - g) : 0;
+        const int kb = (int)min((uintptr_t)16, b - g + 1);
+        if (lane_max16(keep_bytes(q, ka, kb)) >= v) return false;
+    }
     return true;
 }
 
