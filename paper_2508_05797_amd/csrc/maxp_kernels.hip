@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_maxp_verify(Plan P, const uint8_t* bmax
     }
 }
 
-// The MAXP chain over the candidates (one wave per job).  From a chunk start
+// The MAXP chain over the candidates (one block per job, one wave walking).  From a chunk start
 // s a candidate q is a boundary iff (q - s) mod M >= w: the forced cuts
 // s+M, s+2M, ... in between leave it at least w bytes into its chunk.  After
 // a boundary the next candidate is accepted directly unless it lies more
@@ -258,54 +258,79 @@ __device__ __forceinline__ void put_forced(uint64_t* out, uint64_t& cnt,
     cnt += (uint64_t)t;
 }
 
+constexpr uint32_t kChainChunk = 4096;   // segment counts staged at a time
+constexpr uint32_t kChainThreads = 256;  // threads per block of the chain pass
+
+// All threads of the block call this; the block stages the segments'
+// candidate counts in LDS (one parallel read per kChainChunk segments) and
+// wave 0 walks them.
 __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
-                               const uint32_t* cand, uint32_t* err) {
+                               const uint32_t* cand, uint32_t* err,
+                               uint32_t* lds_nc) {
     const int64_t n = J.n, w = J.w, M = J.M;
+    const bool walker = threadIdx.x < kWave;
     uint64_t* out = J.cuts;
     const uint64_t room = max_cuts_of(J);
     uint64_t cnt = 0;
     int64_t s = 0;
-    for (uint32_t sb = 0; sb < J.nseg; sb += kWave) {
-        const uint32_t my = sb + lane_id();
-        const uint32_t my_nc = my < J.nseg ? meta[J.item0 + my].nspec : 0u;
-        uint64_t has = __ballot(my_nc != 0);
-        while (has) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(has);
-            has &= has - 1;
-            const uint32_t seg = sb + l;
-            const uint32_t nc = __builtin_amdgcn_readlane(my_nc, l);
-            const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
-            const int64_t a = (int64_t)seg * J.seg;
-            for (uint32_t base = 0; base < nc; base += kWave) {
-                const uint32_t k = base + lane_id();
-                const bool valid = k < nc;
-                const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
-                int64_t qprev = __shfl_up(q, 1);
-                uint32_t done = 0;  // lanes below `done` are settled
-                for (;;) {
-                    const bool acc = valid && lane_id() >= done && q >= s &&
-                                     ((q - s) % M) >= w;
-                    const uint64_t ball = __ballot(acc);
-                    if (ball == 0) break;
-                    const uint32_t f = (uint32_t)__builtin_ctzll(ball);
-                    const int64_t qf = uni64(__shfl(q, (int)f));
-                    // accepted run: f, then every next candidate within M+1
-                    const bool brk = lane_id() > f &&
-                                     (!valid || (q - qprev - 1) >= M);
-                    const uint64_t bb = __ballot(brk);
-                    const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
-                    put_forced(out, cnt, room, s, (qf - s) / M, M);
-                    if (lane_id() >= f && lane_id() < g &&
-                        cnt + (lane_id() - f) < room)
-                        out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
-                    cnt += g - f;
-                    s = uni64(__shfl(q, (int)(g - 1))) + 1;
-                    done = g;
-                    if (g >= 64) break;
+    for (uint32_t cb = 0; cb < J.nseg; cb += kChainChunk) {
+        const uint32_t m = min(kChainChunk, J.nseg - cb);
+        uint32_t v[kChainChunk / kChainThreads];   // all loads in flight first
+#pragma unroll
+        for (uint32_t k = 0; k < kChainChunk / kChainThreads; k++) {
+            const uint32_t i = threadIdx.x + k * kChainThreads;
+            v[k] = i < m ? meta[J.item0 + cb + i].nspec : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kChainChunk / kChainThreads; k++) {
+            const uint32_t i = threadIdx.x + k * kChainThreads;
+            if (i < m) lds_nc[i] = v[k];
+        }
+        __syncthreads();
+        for (uint32_t sb = 0; walker && sb < m; sb += kWave) {
+            const uint32_t my = sb + lane_id();
+            const uint32_t my_nc = my < m ? lds_nc[my] : 0u;
+            uint64_t has = __ballot(my_nc != 0);
+            while (has) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(has);
+                has &= has - 1;
+                const uint32_t seg = cb + sb + l;
+                const uint32_t nc = __builtin_amdgcn_readlane(my_nc, l);
+                const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
+                const int64_t a = (int64_t)seg * J.seg;
+                for (uint32_t base = 0; base < nc; base += kWave) {
+                    const uint32_t k = base + lane_id();
+                    const bool valid = k < nc;
+                    const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
+                    int64_t qprev = __shfl_up(q, 1);
+                    uint32_t done = 0;  // lanes below `done` are settled
+                    for (;;) {
+                        const bool acc = valid && lane_id() >= done && q >= s &&
+                                         ((q - s) % M) >= w;
+                        const uint64_t ball = __ballot(acc);
+                        if (ball == 0) break;
+                        const uint32_t f = (uint32_t)__builtin_ctzll(ball);
+                        const int64_t qf = uni64(__shfl(q, (int)f));
+                        // accepted run: f, then every next candidate within M+1
+                        const bool brk = lane_id() > f &&
+                                         (!valid || (q - qprev - 1) >= M);
+                        const uint64_t bb = __ballot(brk);
+                        const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
+                        put_forced(out, cnt, room, s, (qf - s) / M, M);
+                        if (lane_id() >= f && lane_id() < g &&
+                            cnt + (lane_id() - f) < room)
+                            out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
+                        cnt += g - f;
+                        s = uni64(__shfl(q, (int)(g - 1))) + 1;
+                        done = g;
+                        if (g >= 64) break;
+                    }
                 }
             }
         }
+        __syncthreads();                 // lds_nc is refilled next
     }
+    if (!walker) return;
     if (n > 0) {
         put_forced(out, cnt, room, s, (n - s - 1) / M, M);
         if (lane_id() == 0 && cnt < room) out[cnt] = (uint64_t)n;
@@ -318,16 +343,17 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
     if (lane_id() == 0) *J.n_cuts = cnt;
 }
 
-__global__ __launch_bounds__(256) void k_maxp_chain(Plan P, uint32_t n_jobs_h,
+__global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n_jobs_h,
                                                     const uint32_t* n_jobs_d,
                                                     const SegMeta* meta,
                                                     const uint32_t* cand,
                                                     uint32_t* err) {
+    __shared__ uint32_t nc[kChainChunk];
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
-    for (uint32_t job = wave_global_id(); job < n_jobs; job += wave_count()) {
-        JobView J = view(P.jobs ? P.jobs[job] : P.one);
-        if (!J.ok || J.algo != kMaxp || J.n == 0) continue;
-        maxp_chain_job(J, meta, cand, err);
+    for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
+        const JobView J = view(P.jobs ? P.jobs[job] : P.one);
+        if (!J.ok || J.algo != kMaxp || J.n == 0) continue;   // alike for the block
+        maxp_chain_job(J, meta, cand, err, nc);
     }
 }
 
@@ -372,8 +398,8 @@ hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                    bmax, bpos, err);
     CDC_LAUNCH(mk, any_blocks ? 2 : 1, "maxp_verify", k_maxp_verify, grid, blk,
                0, st, P, bmax, bpos, meta, cand, err);
-    const uint32_t jgrid = min((jobs_upper + 3) / 4, 2048u);
-    CDC_LAUNCH(mk, 2, "maxp_chain", k_maxp_chain, dim3(jgrid), dim3(256), 0, st,
+    const uint32_t jgrid = min(jobs_upper, 2048u);
+    CDC_LAUNCH(mk, 2, "maxp_chain", k_maxp_chain, dim3(jgrid), dim3(kChainThreads), 0, st,
                P, jobs_upper, n_jobs_d, meta, cand, err);
     return hipGetLastError();
 }
