@@ -32,12 +32,19 @@ __device__ void block_summaries(const uint4& v, int64_t tp, int64_t n,
         x = keep_bytes(v, a, b);
     }
     const uint32_t lm = lane_max16(x);
-    const uint32_t gm_partial = seg_max<G>(lm);
     const uint32_t last = lane_id() | (G - 1);
-    const uint32_t gm = (uint32_t)__shfl((int)gm_partial, (int)last);
-    const uint32_t eq = (lm == gm) ? 1u : 0u;
-    const uint32_t cnt_partial = seg_sum<G>(eq);
-    const uint32_t cnt = (uint32_t)__shfl((int)cnt_partial, (int)last);
+    uint32_t gm, eq, cnt;
+    if constexpr (G == kWave) {
+        // one block per tile: the maximum is uniform, the lanes holding it
+        // are counted from a ballot
+        gm = (uint32_t)__builtin_amdgcn_readlane((int)seg_max<G>(lm), kWave - 1);
+        eq = (lm == gm) ? 1u : 0u;
+        cnt = (uint32_t)__builtin_popcountll(__ballot(eq != 0));
+    } else {
+        gm = (uint32_t)__shfl((int)seg_max<G>(lm), (int)last);
+        eq = (lm == gm) ? 1u : 0u;
+        cnt = (uint32_t)__shfl((int)seg_sum<G>(eq), (int)last);
+    }
     const int64_t beta = beta0 + (int64_t)(lane_id() / G);
     if (cnt != 1) {
         if (lane_id() == last) {
