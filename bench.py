@@ -6,12 +6,16 @@ Three legs, all on seeded synthetic data resident in HBM before timing:
           blocks (50% uniform random, 30% Zipf(1.1) text over 64 symbols,
           20% constant runs) with RAM (w=4096), AE-Max (w=4096) and MAXP
           (w=2048 each side), max chunk 64 KiB: three passes of the whole hot
-          path over the same bytes.  value = bytes chunked per second over
-          the timed steps (GB = 1e9 B).
+          path over the same bytes, as one cdc_chunk_batch of three jobs.
+          value = bytes chunked per second over the timed steps (GB = 1e9
+          B).  The same chunkings as three single cdc_chunk calls in order
+          give the sequential rate, the per-algorithm rates and the kernel
+          times of the roofline.
   batch   20,000 files of log-normal sizes (median 64 KiB, sigma 2.0,
-          clipped to 1 KiB .. 256 MiB; uniform random bytes), each algorithm
-          as one cdc_chunk_batch, tuned by cdc_autotune and captured in a HIP
-          graph, against one cdc_chunk call per file (the plain path).
+          clipped to 1 KiB .. 256 MiB; uniform random bytes), every file
+          under every algorithm as one cdc_chunk_batch of 60,000 jobs, tuned
+          by cdc_autotune and captured in a HIP graph, against one cdc_chunk
+          call per file and algorithm (the plain path).
   serve   open-loop Poisson arrivals of requests (sizes as the batch leg,
           algorithm uniform over RAM / AE / MAXP, bytes at random places of
           the resident batch buffer) at 25 / 50 / 90 % of the measured
@@ -21,7 +25,8 @@ Three legs, all on seeded synthetic data resident in HBM before timing:
 
 Also reported: the roofline of the stream leg's dominant kernel (its
 algorithmic bytes, the stream read once, over its average duration from HIP
-events on the launch stream, against the 8 TB/s HBM peak; traffic from
+events on the launch stream during the single-call timed region, against the
+8 TB/s HBM peak; traffic from
 rocprofv3 FETCH_SIZE / WRITE_SIZE when they were taken on the current kernel
 source), and the oracle timed on this host (cpu_baseline), whose cuts also
 check the GPU's bit for bit.
@@ -101,8 +106,18 @@ def stream_leg(args, binding, datagen, torch, np):
     d = torch.from_numpy(x).to(dev)
     bufs = {a: (torch.empty(binding.max_cuts(n, w), dtype=torch.int64, device=dev),
                 torch.empty(1, dtype=torch.int64, device=dev)) for a, w in ALGOS}
+    # the step: the stream under the three algorithms as one batched call
+    # (three jobs on the same bytes; the library runs the algorithms side by
+    # side)
+    b3 = binding.Batch(d, [0] * len(ALGOS), [n] * len(ALGOS),
+                       [a for a, _w in ALGOS], [w for _a, w in ALGOS], MAX_CHUNK)
+    binding.reserve(len(ALGOS) * n + (1 << 20), len(ALGOS),
+                    min(w for _a, w in ALGOS), MAX_CHUNK)
 
-    def step(only=None):
+    def step():
+        b3.run()
+
+    def single(only=None):
         for algo, w in ALGOS:
             if only and algo != only:
                 continue
@@ -111,18 +126,28 @@ def stream_leg(args, binding, datagen, torch, np):
 
     for _ in range(args.warmup):
         step()
+        single()
     torch.cuda.synchronize()
-    # timed region: K steps, HIP events around each call's main kernel
-    binding.set_profiling(1)
-    binding.kernel_times()
+    # timed region: K steps
     t0, t1 = events()
-    torch.cuda.synchronize()
     t0.record()
     for _ in range(args.steps):
         step()
     t1.record()
     torch.cuda.synchronize()
     ms_step = t0.elapsed_time(t1) / args.steps
+    # the same chunkings as three single calls in order: the sequential rate,
+    # and HIP events around each call's main kernel (no other algorithm's
+    # kernels beside it) for the roofline
+    binding.set_profiling(1)
+    binding.kernel_times()
+    t0, t1 = events()
+    t0.record()
+    for _ in range(args.steps):
+        single()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_seq = t0.elapsed_time(t1) / args.steps
     ktimes = binding.kernel_times()
     binding.set_profiling(0)
 
@@ -131,12 +156,12 @@ def stream_leg(args, binding, datagen, torch, np):
         e0, e1 = events()
         e0.record()
         for _ in range(args.steps):
-            step(algo)
+            single(algo)
         e1.record()
         torch.cuda.synchronize()
         per_algo[algo] = round(n / (e0.elapsed_time(e1) / args.steps * 1e-3) / 1e9, 2)
         binding.set_profiling(2)
-        step(algo)
+        single(algo)
         breakdown[algo] = {k: round(v[1] / max(v[0], 1), 4)
                            for k, v in binding.kernel_times().items()}
         binding.set_profiling(0)
@@ -152,13 +177,20 @@ def stream_leg(args, binding, datagen, torch, np):
             "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": n,
             "traffic": (traffic or {}).get("bytes_per_launch", {}).get(dom)}
-    gpu_cuts = {a: bufs[a][0][:int(bufs[a][1].item())].cpu().numpy().astype(np.uint64)
-                for a, _ in ALGOS}
+    torch.cuda.synchronize()
+    assert (b3.statuses() == 0).all(), "batched step failed"
+    gpu_cuts = {}
+    for j, (a, _w) in enumerate(ALGOS):
+        got = b3.result(j)
+        assert torch.equal(got, bufs[a][0][:int(bufs[a][1].item())]), \
+            "batched and single call differ: " + a
+        gpu_cuts[a] = got.cpu().numpy().astype(np.uint64)
     assert binding.device_errors() == 0
     value = len(ALGOS) * n / (ms_step * 1e-3) / 1e9
-    del d, bufs
-    return dict(x=x, value=value, ms_step=ms_step, roof=roof, per_algo=per_algo,
-                breakdown=breakdown,
+    seq = len(ALGOS) * n / (ms_seq * 1e-3) / 1e9
+    del d, bufs, b3
+    return dict(x=x, value=value, ms_step=ms_step, seq_gbs=seq, roof=roof,
+                per_algo=per_algo, breakdown=breakdown,
                 kernel_avg_ms={k: round(v, 4) for k, v in per_kernel.items()},
                 gpu_cuts=gpu_cuts)
 
@@ -399,6 +431,10 @@ def main():
         out["value"] = round(s["value"], 2)
         out["ms_per_step"] = round(s["ms_step"], 4)
         out["roofline"] = s["roof"]
+        out["step"] = ("one cdc_chunk_batch over the three (stream, algorithm) "
+                       "jobs; roofline and per-algorithm rates from the same "
+                       "chunkings as single cdc_chunk calls")
+        out["sequential_gbs"] = round(s["seq_gbs"], 2)
         out["per_algorithm_gbs"] = s["per_algo"]
         out["kernel_avg_ms"] = s["kernel_avg_ms"]
         out["kernel_breakdown_ms"] = s["breakdown"]
