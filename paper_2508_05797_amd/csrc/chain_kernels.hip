@@ -37,6 +37,7 @@
 namespace cdc {
 
 constexpr int kSpan = 8;         // tiles a walker considers at once (one word of maxima)
+static_assert(kSpan == 8, "a span's tile maxima are one packed 64-bit word");
 constexpr int kGroup = 8;        // tiles staged per step (speculation)
 constexpr int kGroupSolo = 16;   // same for the lone fix-up / re-walk walkers
 
