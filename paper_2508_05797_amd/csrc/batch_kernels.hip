@@ -173,28 +173,51 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scan(
 }
 
 // (3) Every job gets its final offsets and status; empty or rejected jobs
-// get zero cuts; the item table lists (job, segment) for every segment.
+// get zero cuts; the item table lists (job, segment) for every segment.  A
+// thread writes the first kOwnItems items of its job; the items of larger
+// jobs past those are written by the whole block.
+constexpr uint32_t kOwnItems = 64;
+
 __global__ __launch_bounds__(kPlanThreads) void k_plan_items(
     cdc_job* jobs, uint32_t n_jobs, JobDesc* jd, Item* items,
     const Counts* bsum, const uint32_t* ctl) {
+    __shared__ uint32_t big_job[kPlanThreads], big_n[kPlanThreads], big_first[kPlanThreads];
+    __shared__ uint32_t n_big;
     const uint32_t j = blockIdx.x * kPlanThreads + threadIdx.x;
-    if (j >= n_jobs) return;
-    const bool over = ctl[1] != 0;
-    JobDesc d = jd[j];
-    const Counts o = bsum[blockIdx.x];
-    const bool valid = d.ok != 0;
-    if (valid) d.item0 += ctl[2 + d.algo] + (uint32_t)o.v[d.algo];
-    d.slot0 += o.v[kSlots];
-    d.blk0 += o.v[kBlocks];
-    if (over) d.ok = 0;
-    jd[j] = d;
-    jobs[j].status = over ? CDC_ENOMEM : (valid ? CDC_OK : CDC_EINVAL);
-    if (!d.ok || d.n == 0) {
-        if (d.n_cuts) *d.n_cuts = 0;
-        return;
+    if (threadIdx.x == 0) n_big = 0;
+    __syncthreads();
+    if (j < n_jobs) {
+        const bool over = ctl[1] != 0;
+        JobDesc d = jd[j];
+        const Counts o = bsum[blockIdx.x];
+        const bool valid = d.ok != 0;
+        if (valid) d.item0 += ctl[2 + d.algo] + (uint32_t)o.v[d.algo];
+        d.slot0 += o.v[kSlots];
+        d.blk0 += o.v[kBlocks];
+        if (over) d.ok = 0;
+        jd[j] = d;
+        jobs[j].status = over ? CDC_ENOMEM : (valid ? CDC_OK : CDC_EINVAL);
+        if (!d.ok || d.n == 0) {
+            if (d.n_cuts) *d.n_cuts = 0;
+        } else {
+            Item* it = items + d.item0;
+            const uint32_t own = min(d.nseg, kOwnItems);
+            for (uint32_t sg = 0; sg < own; sg++) it[sg] = Item{j, sg};
+            if (d.nseg > kOwnItems) {
+                const uint32_t k = atomicAdd(&n_big, 1u);
+                big_job[k] = j;
+                big_n[k] = d.nseg;
+                big_first[k] = d.item0;
+            }
+        }
     }
-    Item* it = items + d.item0;
-    for (uint32_t s = 0; s < d.nseg; s++) it[s] = Item{j, s};
+    __syncthreads();
+    const uint32_t nb = n_big;
+    for (uint32_t k = 0; k < nb; k++) {
+        const uint32_t jj = big_job[k], ns = big_n[k], i0 = big_first[k];
+        for (uint32_t sg = kOwnItems + threadIdx.x; sg < ns; sg += blockDim.x)
+            items[i0 + sg] = Item{jj, sg};
+    }
 }
 
 hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
