@@ -122,10 +122,11 @@ typedef struct {
  * cdc_reserve(stream, ...) reserved room for the largest batch first.
  * Without a reservation and outside capture, the call reads the
  * descriptors back (a synchronous copy) to size the workspace.  The RAM,
- * AE, AE-Min and MAXP jobs of a batch run side by side on three
- * library-owned streams per `stream` (default priority), forked from and
- * joined back into `stream` by events; they are made by the first batch
- * outside capture (before that, the algorithms run in order).
+ * AE, AE-Min and MAXP jobs of a batch run side by side: RAM on `stream`, AE
+ * and AE-Min on one and MAXP on another of two library-owned streams per
+ * `stream` (default priority), forked from and joined back into `stream` by
+ * events; they are made by the first batch outside capture (before that,
+ * the algorithms run in order).
  * Returns CDC_OK once enqueued, CDC_EINVAL (jobs null, n_jobs 0),
  * CDC_ENOMEM (capture without enough reservation) or CDC_EHIP.
  */

@@ -87,26 +87,31 @@ struct EventMarks : Marks {
 int g_profile_level = 0;
 
 // Streams of a workspace for running the algorithms of a batch side by
-// side: AE, AE-Min and MAXP go to their own streams, forked from and joined
-// back into the caller's stream by events (under capture this becomes
-// parallel branches of the graph).  Default priority, non-blocking.
+// side: RAM stays on the caller's stream, AE and AE-Min go to one side
+// stream, MAXP to the other; they are forked from and joined back into the
+// caller's stream by events (under capture this becomes parallel branches
+// of the graph).  Two, so that with the caller's stream they fit the few
+// hardware queues a process gets.  Default priority, non-blocking.
+constexpr int kSide = 2;
+
 struct SideStreams {
     bool ok = false;
-    hipStream_t s[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    hipStream_t s[kSide] = {};
+    hipEvent_t fork = nullptr, mid = nullptr, join[kSide] = {};
 
     bool create() {
-        for (int i = 0; i < 3; i++)
+        for (int i = 0; i < kSide; i++)
             if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess)
                 return false;
-        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&mid, hipEventDisableTiming) != hipSuccess)
             return false;
         ok = true;
         return true;
     }
     void destroy() {
-        for (int i = 0; i < 3; i++) {
+        for (int i = 0; i < kSide; i++) {
             if (s[i]) {
                 (void)hipStreamSynchronize(s[i]);
                 (void)hipStreamDestroy(s[i]);
@@ -116,7 +121,8 @@ struct SideStreams {
             join[i] = nullptr;
         }
         if (fork) (void)hipEventDestroy(fork);
-        fork = nullptr;
+        if (mid) (void)hipEventDestroy(mid);
+        fork = mid = nullptr;
         ok = false;
     }
 };
@@ -550,18 +556,28 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
                            at<uint8_t>(ws.dev, L.bmax), at<int64_t>(ws.dev, L.bpos),
                            cw.err, wpb, caps.blocks != 0, st, mk);
     };
+    auto chain = [&](uint32_t algo, hipStream_t st, int part) {
+        return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk, part);
+    };
     if (side && sd.ok) {
+        // The speculation passes are enqueued first, so that the host's
+        // enqueueing does not hold back their start.  MAXP starts once RAM's
+        // fix-up is done: its streaming pass, with many short workgroups,
+        // would otherwise take the workgroup slots that the fix-up's walkers
+        // (on RAM's critical path) wait for.
         e = hipEventRecord(sd.fork, stream);
-        for (int i = 0; i < 3 && e == hipSuccess; i++)
+        for (int i = 0; i < kSide && e == hipSuccess; i++)
             e = hipStreamWaitEvent(sd.s[i], sd.fork, 0);
-        if (e == hipSuccess)
-            e = launch_chain(P, kRam, grid_waves, n_jobs, nullptr, cw, stream, mk);
-        if (e == hipSuccess)
-            e = launch_chain(P, kAe, grid_waves, n_jobs, nullptr, cw, sd.s[0], mk);
-        if (e == hipSuccess)
-            e = launch_chain(P, kAeMin, grid_waves, n_jobs, nullptr, cw, sd.s[1], mk);
-        if (e == hipSuccess) e = maxp(sd.s[2]);
-        for (int i = 0; i < 3 && e == hipSuccess; i++) {
+        if (e == hipSuccess) e = chain(kRam, stream, kPartSpec);
+        if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartSpec);
+        if (e == hipSuccess) e = chain(kRam, stream, kPartFix);
+        if (e == hipSuccess) e = hipEventRecord(sd.mid, stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sd.s[1], sd.mid, 0);
+        if (e == hipSuccess) e = maxp(sd.s[1]);
+        if (e == hipSuccess) e = chain(kRam, stream, kPartRest);
+        if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
+        if (e == hipSuccess) e = chain(kAeMin, sd.s[0], kPartAll);
+        for (int i = 0; i < kSide && e == hipSuccess; i++) {
             e = hipEventRecord(sd.join[i], sd.s[i]);
             if (e == hipSuccess) e = hipStreamWaitEvent(stream, sd.join[i], 0);
         }

@@ -109,6 +109,10 @@ struct ChainWs {
 // Parallel resolution rounds after the fix-up before the ordered pass.
 constexpr int kRounds = 2;
 
+// Parts of a RAM / AE launch sequence: the speculation pass (streaming over
+// the bytes), the fix-up pass, and the rounds with the settling pass.
+enum : int { kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartAll = 7 };
+
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int waves_per_block,
@@ -117,7 +121,8 @@ hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
 // all RAM / AE items (launch_ram_ae is the three and the copy in order).
 hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
-                        const ChainWs& ws, hipStream_t st, Marks* marks);
+                        const ChainWs& ws, hipStream_t st, Marks* marks,
+                        int part = kPartAll);
 hipError_t launch_emit(const Plan& P, uint32_t items_upper, const ChainWs& ws,
                        int waves_per_block, hipStream_t st, Marks* marks);
 hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,

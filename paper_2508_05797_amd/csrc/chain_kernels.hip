@@ -1131,6 +1131,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_spec(Plan P, ChainWs ws) {
 // (segment 0 from the job start).
 template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_fix(Plan P, ChainWs ws) {
+    tail_priority();
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
@@ -1144,6 +1145,7 @@ __global__ __launch_bounds__(kCoopThreads) void k_fix(Plan P, ChainWs ws) {
 // r-1) differs from the entry it was resolved from is resolved again.
 template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_round(Plan P, ChainWs ws, int r) {
+    tail_priority();
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const int src = (r - 1) & 1, dst = r & 1;
@@ -1253,6 +1255,7 @@ template <bool RAM, bool INV>
 __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
                                                  const uint32_t* n_jobs_d,
                                                  ChainWs ws) {
+    tail_priority();
     __shared__ Ring<kGroupSolo> lds[1];
     __shared__ uint64_t sh[256];
     __shared__ uint32_t flagged[256];
@@ -1312,12 +1315,15 @@ __global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
 template <bool RAM, bool INV, bool ONE>
 static void launch_passes(const Plan& P, uint32_t items_upper,
                           const ChainWs& ws, hipStream_t st, Marks* mk,
-                          const char* spec_name) {
+                          const char* spec_name, int part) {
     const dim3 blk(kCoopThreads), grid(items_upper);
-    CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
-    CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
-    for (int r = 2; r < 2 + kRounds; r++)
-        CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
+    if (part & kPartSpec)
+        CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+    if (part & kPartFix)
+        CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+    if (part & kPartRest)
+        for (int r = 2; r < 2 + kRounds; r++)
+            CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
 }
 
 // With one job, items_upper is its segment count (the grid covers every
@@ -1326,29 +1332,30 @@ template <bool RAM, bool INV>
 static void launch_algo(const Plan& P, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
                         const ChainWs& ws, hipStream_t st, Marks* mk,
-                        const char* spec_name) {
+                        const char* spec_name, int part) {
     if (P.jobs == nullptr)
-        launch_passes<RAM, INV, true>(P, items_upper, ws, st, mk, spec_name);
+        launch_passes<RAM, INV, true>(P, items_upper, ws, st, mk, spec_name, part);
     else
-        launch_passes<RAM, INV, false>(P, items_upper, ws, st, mk, spec_name);
-    CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
-               dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
-               n_jobs_d, ws);
+        launch_passes<RAM, INV, false>(P, items_upper, ws, st, mk, spec_name, part);
+    if (part & kPartRest)
+        CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
+                   dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
+                   n_jobs_d, ws);
 }
 
 hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
-                        const ChainWs& ws, hipStream_t st, Marks* mk) {
+                        const ChainWs& ws, hipStream_t st, Marks* mk, int part) {
     const bool one = P.jobs == nullptr;
     if (algo == kRam)
         launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
-                                 mk, one ? "speculate_ram" : "speculate_batch_ram");
+                                 mk, one ? "speculate_ram" : "speculate_batch_ram", part);
     else if (algo == kAe)
         launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
-                                  mk, one ? "speculate_ae" : "speculate_batch_ae");
+                                  mk, one ? "speculate_ae" : "speculate_batch_ae", part);
     else
         launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, st,
-                                 mk, one ? "speculate_ae_min" : "speculate_batch_ae_min");
+                                 mk, one ? "speculate_ae_min" : "speculate_batch_ae_min", part);
     return hipGetLastError();
 }
 

@@ -355,6 +355,7 @@ __global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n
                                                     const SegMeta* meta,
                                                     const uint32_t* cand,
                                                     uint32_t* err) {
+    tail_priority();
     __shared__ uint32_t nc[kChainChunk];
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {

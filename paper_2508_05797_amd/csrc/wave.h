@@ -15,6 +15,12 @@ namespace cdc {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// The passes that follow a streaming pass (a few long walkers, one block
+// per job) raise their waves' issue priority: where a batch runs them beside
+// another algorithm's streaming pass on the same SIMDs, their instructions
+// issue first and the streaming waves fill the gaps.
+__device__ __forceinline__ void tail_priority() { __builtin_amdgcn_s_setprio(3); }
+
 __device__ __forceinline__ uint32_t uni(uint32_t v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
