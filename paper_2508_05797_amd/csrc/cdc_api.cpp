@@ -97,15 +97,14 @@ constexpr int kSide = 2;
 struct SideStreams {
     bool ok = false;
     hipStream_t s[kSide] = {};
-    hipEvent_t fork = nullptr, mid = nullptr, join[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
 
     bool create() {
         for (int i = 0; i < kSide; i++)
             if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess)
                 return false;
-        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&mid, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
             return false;
         ok = true;
         return true;
@@ -121,8 +120,7 @@ struct SideStreams {
             join[i] = nullptr;
         }
         if (fork) (void)hipEventDestroy(fork);
-        if (mid) (void)hipEventDestroy(mid);
-        fork = mid = nullptr;
+        fork = nullptr;
         ok = false;
     }
 };
@@ -560,21 +558,15 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
         return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk, part);
     };
     if (side && sd.ok) {
-        // The speculation passes are enqueued first, so that the host's
-        // enqueueing does not hold back their start.  MAXP starts once RAM's
-        // fix-up is done: its streaming pass, with many short workgroups,
-        // would otherwise take the workgroup slots that the fix-up's walkers
-        // (on RAM's critical path) wait for.
+        // The streaming passes are enqueued first, so that the host's
+        // enqueueing does not hold back their start.
         e = hipEventRecord(sd.fork, stream);
         for (int i = 0; i < kSide && e == hipSuccess; i++)
             e = hipStreamWaitEvent(sd.s[i], sd.fork, 0);
         if (e == hipSuccess) e = chain(kRam, stream, kPartSpec);
         if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartSpec);
-        if (e == hipSuccess) e = chain(kRam, stream, kPartFix);
-        if (e == hipSuccess) e = hipEventRecord(sd.mid, stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(sd.s[1], sd.mid, 0);
         if (e == hipSuccess) e = maxp(sd.s[1]);
-        if (e == hipSuccess) e = chain(kRam, stream, kPartRest);
+        if (e == hipSuccess) e = chain(kRam, stream, kPartFix | kPartRest);
         if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
         if (e == hipSuccess) e = chain(kAeMin, sd.s[0], kPartAll);
         for (int i = 0; i < kSide && e == hipSuccess; i++) {
