@@ -65,7 +65,7 @@ def test_batch_mixed_algorithms():
     assert binding.device_errors() == 0
 
 
-@pytest.mark.parametrize("algo", ["ram", "ae", "maxp"])
+@pytest.mark.parametrize("algo", ["ram", "ae", "maxp", "ae_min"])
 def test_batch_equals_plain(algo):
     host, offs, sizes = make_files(120, 11)
     d = torch.from_numpy(host).cuda()
@@ -80,6 +80,30 @@ def test_batch_equals_plain(algo):
     for j in range(len(sizes)):
         assert torch.equal(b1.result(j), b2.result(j)), j
     check_batch(b1, host, offs, sizes, [algo] * 120, [w] * 120, [65536] * 120)
+
+
+def test_batches_on_two_streams():
+    """Two batches enqueued at once on two caller streams (each stream has
+    its own workspace and side streams) both give the oracle's offsets."""
+    host, offs, sizes = make_files(200, 21)
+    rng = np.random.default_rng(22)
+    algos = [["ram", "ae", "maxp", "ae_min"][i] for i in rng.integers(0, 4, 200)]
+    windows = [ALGO_W[a] for a in algos]
+    d = torch.from_numpy(host).cuda()
+    ba = binding.Batch(d, offs, sizes, algos, windows, 65536)
+    bb = binding.Batch(d, offs[::-1].copy(), sizes[::-1].copy(), algos[::-1],
+                       windows[::-1], 65536)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    say("case two streams", ba.n_jobs, ba.total_bytes)
+    torch.cuda.synchronize()
+    for _ in range(2):                   # the first run makes the side streams
+        ba.run(stream=sa)
+        bb.run(stream=sb)
+    torch.cuda.synchronize()
+    check_batch(ba, host, offs, sizes, algos, windows, [65536] * 200)
+    check_batch(bb, host, offs[::-1], sizes[::-1], algos[::-1], windows[::-1],
+                [65536] * 200)
+    assert binding.device_errors(sa) == 0 and binding.device_errors(sb) == 0
 
 
 def test_batch_many_jobs():
