@@ -398,7 +398,7 @@ def main():
                          "times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X "
+        print("bench.py measures one GPU: the library runs on a single MI355X "
               "and has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
