@@ -6,7 +6,8 @@ Three legs, all on seeded synthetic data resident in HBM before timing:
           blocks (50% uniform random, 30% Zipf(1.1) text over 64 symbols,
           20% constant runs) with RAM (w=4096), AE-Max (w=4096) and MAXP
           (w=2048 each side), max chunk 64 KiB: three passes of the whole hot
-          path over the same bytes, as one cdc_chunk_batch of three jobs.
+          path over the same bytes, as one cdc_chunk_batch of three jobs
+          (its segment lengths chosen by cdc_autotune before timing).
           value = bytes chunked per second over the timed steps (GB = 1e9
           B).  The same chunkings as three single cdc_chunk calls in order
           give the sequential rate, the per-algorithm rates and the kernel
@@ -111,8 +112,10 @@ def stream_leg(args, binding, datagen, torch, np):
     # side)
     b3 = binding.Batch(d, [0] * len(ALGOS), [n] * len(ALGOS),
                        [a for a, _w in ALGOS], [w for _a, w in ALGOS], MAX_CHUNK)
-    binding.reserve(len(ALGOS) * n + (1 << 20), len(ALGOS),
-                    min(w for _a, w in ALGOS), MAX_CHUNK)
+    # tuned for this batch (the reservation keeps the chosen segment
+    # lengths); the single calls below run with the built-in tuning
+    step_tuning = binding.autotune(b3, reps=3)
+    binding.set_tuning(0, 0, 0)
 
     def step():
         b3.run()
@@ -190,6 +193,7 @@ def stream_leg(args, binding, datagen, torch, np):
     seq = len(ALGOS) * n / (ms_seq * 1e-3) / 1e9
     del d, bufs, b3
     return dict(x=x, value=value, ms_step=ms_step, seq_gbs=seq, roof=roof,
+                step_tuning=step_tuning,
                 per_algo=per_algo, breakdown=breakdown,
                 kernel_avg_ms={k: round(v, 4) for k, v in per_kernel.items()},
                 gpu_cuts=gpu_cuts)
@@ -434,6 +438,7 @@ def main():
         out["step"] = ("one cdc_chunk_batch over the three (stream, algorithm) "
                        "jobs; roofline and per-algorithm rates from the same "
                        "chunkings as single cdc_chunk calls")
+        out["step_tuning"] = s["step_tuning"]
         out["sequential_gbs"] = round(s["seq_gbs"], 2)
         out["per_algorithm_gbs"] = s["per_algo"]
         out["kernel_avg_ms"] = s["kernel_avg_ms"]

@@ -91,7 +91,8 @@ extern "C" int cdc_autotune(const cdc_job* jobs, uint32_t n_jobs,
     const std::vector<uint64_t> chain_segs = {256 << 10, 512 << 10, 1 << 20,
                                               2 << 20, 4 << 20};
     const std::vector<uint64_t> maxp_segs = {16 << 10, 32 << 10, 64 << 10,
-                                             128 << 10, 256 << 10};
+                                             128 << 10, 256 << 10, 512 << 10,
+                                             1 << 20};
     const std::vector<uint32_t> waves = {1, 2, 4};
     // one coordinate at a time
     for (int dim = 0; dim < 3 && rc == CDC_OK; dim++) {
