@@ -226,7 +226,8 @@ def test_autotune_then_capture():
             say("case autotune")
             t1 = binding.autotune(b, reps=1, stream=s)
             assert t1["chain_segment"] in (256 << 10, 512 << 10, 1 << 20, 2 << 20, 4 << 20)
-            assert t1["maxp_segment"] in (16 << 10, 32 << 10, 64 << 10, 128 << 10, 256 << 10)
+            assert t1["maxp_segment"] in (16 << 10, 32 << 10, 64 << 10, 128 << 10,
+                                          256 << 10, 512 << 10, 1 << 20)
             assert t1["waves_per_block"] in (1, 2, 4)
             assert binding.get_tuning() == t1
             assert binding.autotune(b, reps=1, stream=s) == t1
