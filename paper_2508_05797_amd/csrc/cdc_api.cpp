@@ -569,9 +569,12 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
         if (e == hipSuccess) e = chain(kRam, stream, kPartFix | kPartRest);
         if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
         if (e == hipSuccess) e = chain(kAeMin, sd.s[0], kPartAll);
-        for (int i = 0; i < kSide && e == hipSuccess; i++) {
-            e = hipEventRecord(sd.join[i], sd.s[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(stream, sd.join[i], 0);
+        // the side streams join back even after a failed launch, so that no
+        // side work outlives the caller's stream order
+        for (int i = 0; i < kSide; i++) {
+            hipError_t j = hipEventRecord(sd.join[i], sd.s[i]);
+            if (j == hipSuccess) j = hipStreamWaitEvent(stream, sd.join[i], 0);
+            if (e == hipSuccess) e = j;
         }
         if (e == hipSuccess) e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
     } else {
