@@ -190,3 +190,43 @@ def test_mixed_1gib(algo):
     x, _ = datagen.mixed_stream(16384, 2024)
     w = 2048 if algo == "maxp" else 4096
     check(x, algo, w, 65536, tag="C2")
+
+
+@pytest.mark.slow
+def test_past_4gib():
+    """A buffer longer than 2^32 bytes (ragged length), zero except for
+    random stretches across 2^31 and 2^32 and at its end and a constant run
+    of another value: every algorithm's single call, and a batch whose
+    second job starts past 2^32, equal the oracle (positions are 64-bit from
+    the job start to the output)."""
+    n = (1 << 32) + (96 << 20) + 12345
+    x = np.zeros(n, np.uint8)
+    rnd = datagen.uniform(28 << 20, 41)
+    x[(1 << 31) - (2 << 20):(1 << 31) + (2 << 20)] = rnd[:4 << 20]
+    x[(1 << 32) - (8 << 20):(1 << 32) + (8 << 20)] = rnd[4 << 20:20 << 20]
+    x[(1 << 32) + (40 << 20):(1 << 32) + (41 << 20)] = 201
+    x[n - (8 << 20):] = rnd[20 << 20:]
+    d = torch.from_numpy(x).cuda()
+    win = {"ram": 4096, "ae": 4096, "maxp": 2048, "ae_min": 4096}
+    for algo in ALGOS:
+        say("case past 4 GiB", algo, "n=%d" % n)
+        got = binding.chunk(d, algo, win[algo], 65536).cpu().numpy().astype(np.uint64)
+        exp = oracle.chunk(algo, x, win[algo], 65536)
+        assert got.size == exp.size and np.array_equal(got, exp), algo
+        assert int(got[-1]) == n
+    # a batch: a small job, then one from 3 MiB below 2^32 to the end
+    lo = (1 << 32) - (3 << 20) + 7
+    offs = np.array([1000, lo], np.int64)
+    sizes = np.array([5 << 20, n - lo], np.int64)
+    for algo in ["ram", "maxp"]:
+        say("case past 4 GiB batch", algo)
+        b = binding.Batch(d, offs, sizes, algo, win[algo], 65536)
+        b.run()
+        torch.cuda.synchronize()
+        assert (b.statuses() == 0).all()
+        for j in range(2):
+            exp = oracle.chunk(algo, x[offs[j]:offs[j] + sizes[j]], win[algo], 65536)
+            got = b.result(j).cpu().numpy().astype(np.uint64)
+            assert got.size == exp.size and np.array_equal(got, exp), (algo, j)
+    del d
+    torch.cuda.empty_cache()
