@@ -89,7 +89,8 @@ def adversarial(n, w, rng):
 
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("w,M", [(1, 2), (3, 7), (15, 16), (64, 1000),
-                                 (600, 4000), (4096, 65536)])
+                                 (600, 4000), (4096, 65536), (9000, 30000),
+                                 (20000, 70000)])
 def test_adversarial(algo, w, M):
     rng = np.random.default_rng(w * 7 + M)
     n = max(3 * M + 333, 20000)
@@ -228,5 +229,30 @@ def test_past_4gib():
             exp = oracle.chunk(algo, x[offs[j]:offs[j] + sizes[j]], win[algo], 65536)
             got = b.result(j).cpu().numpy().astype(np.uint64)
             assert got.size == exp.size and np.array_equal(got, exp), (algo, j)
+    del d
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("w", [4096, 1 << 20])
+def test_max_chunk_limit(w):
+    """The largest max_chunk (2^28) and a window of 1 MiB: zeros with two
+    255 bytes (after each, RAM scans the zeros up to the forced cut at
+    s + 2^28) and a random stretch, about 640 MiB in all."""
+    M = 1 << 28
+    n = (640 << 20) + 77
+    x = np.zeros(n, np.uint8)
+    x[0] = 255
+    x[300 << 20] = 255
+    x[500 << 20:501 << 20] = datagen.uniform(1 << 20, 43)
+    d = torch.from_numpy(x).cuda()
+    for algo in ALGOS:
+        wa = min(w, 4096) if algo == "maxp" else w
+        say("case max chunk", algo, "w=%d M=%d n=%d" % (wa, M, n))
+        got = binding.chunk(d, algo, wa, M).cpu().numpy().astype(np.uint64)
+        exp = oracle.chunk(algo, x, wa, M)
+        assert got.size == exp.size and np.array_equal(got, exp), algo
+        if algo in ("ram", "maxp"):
+            assert M in np.diff(np.concatenate([[0], exp.astype(np.int64)]))
     del d
     torch.cuda.empty_cache()
