@@ -2,6 +2,8 @@
 on that buffer alone, rejected jobs do not disturb the others, the plain
 one-call-per-job path agrees, and a batch captured into a HIP graph gives
 the same result on every replay."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -247,3 +249,20 @@ def test_autotune_then_capture():
             check_batch(b, host, offs, sizes, algos, windows, [65536] * 150)
     finally:
         binding.set_tuning()
+
+
+def test_capture_needs_reservation():
+    """Under stream capture a batch that no reservation covers is refused
+    with CDC_ENOMEM before anything is enqueued (nothing may allocate)."""
+    host, offs, sizes = make_files(20, 31)
+    d = torch.from_numpy(host).cuda()
+    b = binding.Batch(d, offs, sizes, "ram", 4096, 65536)
+    s = torch.cuda.Stream()              # a stream without a workspace yet
+    torch.cuda.synchronize()
+    say("case capture without reservation")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rc = binding.lib().cdc_chunk_batch(ctypes.c_void_p(b.jobs.data_ptr()),
+                                           b.n_jobs, ctypes.c_void_p(s.cuda_stream))
+    assert rc == -2                      # CDC_ENOMEM
+    assert "cdc_reserve" in binding.lib().cdc_last_error().decode()
