@@ -1120,6 +1120,11 @@ __device__ __forceinline__ void for_items(const Plan& P, uint32_t want, F&& f) {
 
 template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kCoopThreads) void k_spec(Plan P, ChainWs ws) {
+    // One job: the walkers (the pass's bound; two per SIMD beside two
+    // producers) issue ahead of the producers, which have time to spare.
+    // Not in batches, where the later passes of other algorithms take the
+    // highest priority and the producers there have less slack.
+    if (ONE && wave_in_block() == 1) __builtin_amdgcn_s_setprio(2);
     __shared__ Coop<kGroup> lds;
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
