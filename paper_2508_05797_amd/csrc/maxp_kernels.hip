@@ -269,8 +269,9 @@ constexpr uint32_t kChainChunk = 4096;   // segment counts staged at a time
 constexpr uint32_t kChainThreads = 256;  // threads per block of the chain pass
 
 // All threads of the block call this; the block stages the segments'
-// candidate counts in LDS (one parallel read per kChainChunk segments) and
-// wave 0 walks them.
+// candidate counts in LDS (one parallel read per kChainChunk segments, zero
+// past the job's last segment) and wave 0 walks them, four segments per
+// lane at a time (the candidates are sparse, so most steps find none).
 __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                                const uint32_t* cand, uint32_t* err,
                                uint32_t* lds_nc) {
@@ -280,6 +281,39 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
     const uint64_t room = max_cuts_of(J);
     uint64_t cnt = 0;
     int64_t s = 0;
+    // the nc candidates of segment seg, in order
+    auto take = [&](uint32_t seg, uint32_t nc) {
+        const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
+        const int64_t a = (int64_t)seg * J.seg;
+        for (uint32_t base = 0; base < nc; base += kWave) {
+            const uint32_t k = base + lane_id();
+            const bool valid = k < nc;
+            const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
+            int64_t qprev = __shfl_up(q, 1);
+            uint32_t done = 0;  // lanes below `done` are settled
+            for (;;) {
+                const bool acc = valid && lane_id() >= done && q >= s &&
+                                 ((q - s) % M) >= w;
+                const uint64_t ball = __ballot(acc);
+                if (ball == 0) break;
+                const uint32_t f = (uint32_t)__builtin_ctzll(ball);
+                const int64_t qf = uni64(__shfl(q, (int)f));
+                // accepted run: f, then every next candidate within M+1
+                const bool brk = lane_id() > f &&
+                                 (!valid || (q - qprev - 1) >= M);
+                const uint64_t bb = __ballot(brk);
+                const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
+                put_forced(out, cnt, room, s, (qf - s) / M, M);
+                if (lane_id() >= f && lane_id() < g &&
+                    cnt + (lane_id() - f) < room)
+                    out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
+                cnt += g - f;
+                s = uni64(__shfl(q, (int)(g - 1))) + 1;
+                done = g;
+                if (g >= 64) break;
+            }
+        }
+    };
     for (uint32_t cb = 0; cb < J.nseg; cb += kChainChunk) {
         const uint32_t m = min(kChainChunk, J.nseg - cb);
         uint32_t v[kChainChunk / kChainThreads];   // all loads in flight first
@@ -289,50 +323,24 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
             v[k] = i < m ? meta[J.item0 + cb + i].nspec : 0u;
         }
 #pragma unroll
-        for (uint32_t k = 0; k < kChainChunk / kChainThreads; k++) {
-            const uint32_t i = threadIdx.x + k * kChainThreads;
-            if (i < m) lds_nc[i] = v[k];
-        }
+        for (uint32_t k = 0; k < kChainChunk / kChainThreads; k++)
+            lds_nc[threadIdx.x + k * kChainThreads] = v[k];
         __syncthreads();
-        for (uint32_t sb = 0; walker && sb < m; sb += kWave) {
-            const uint32_t my = sb + lane_id();
-            const uint32_t my_nc = my < m ? lds_nc[my] : 0u;
-            uint64_t has = __ballot(my_nc != 0);
+        for (uint32_t sb = 0; walker && sb < m; sb += 4 * kWave) {
+            const uint4 q4 = *(const uint4*)&lds_nc[sb + 4 * lane_id()];
+            uint64_t has = __ballot((q4.x | q4.y | q4.z | q4.w) != 0);
             while (has) {
                 const uint32_t l = (uint32_t)__builtin_ctzll(has);
                 has &= has - 1;
-                const uint32_t seg = cb + sb + l;
-                const uint32_t nc = __builtin_amdgcn_readlane(my_nc, l);
-                const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
-                const int64_t a = (int64_t)seg * J.seg;
-                for (uint32_t base = 0; base < nc; base += kWave) {
-                    const uint32_t k = base + lane_id();
-                    const bool valid = k < nc;
-                    const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
-                    int64_t qprev = __shfl_up(q, 1);
-                    uint32_t done = 0;  // lanes below `done` are settled
-                    for (;;) {
-                        const bool acc = valid && lane_id() >= done && q >= s &&
-                                         ((q - s) % M) >= w;
-                        const uint64_t ball = __ballot(acc);
-                        if (ball == 0) break;
-                        const uint32_t f = (uint32_t)__builtin_ctzll(ball);
-                        const int64_t qf = uni64(__shfl(q, (int)f));
-                        // accepted run: f, then every next candidate within M+1
-                        const bool brk = lane_id() > f &&
-                                         (!valid || (q - qprev - 1) >= M);
-                        const uint64_t bb = __ballot(brk);
-                        const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
-                        put_forced(out, cnt, room, s, (qf - s) / M, M);
-                        if (lane_id() >= f && lane_id() < g &&
-                            cnt + (lane_id() - f) < room)
-                            out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
-                        cnt += g - f;
-                        s = uni64(__shfl(q, (int)(g - 1))) + 1;
-                        done = g;
-                        if (g >= 64) break;
-                    }
-                }
+                const uint32_t seg = cb + sb + 4 * l;
+                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)q4.x, l);
+                const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)q4.y, l);
+                const uint32_t c2 = (uint32_t)__builtin_amdgcn_readlane((int)q4.z, l);
+                const uint32_t c3 = (uint32_t)__builtin_amdgcn_readlane((int)q4.w, l);
+                if (c0) take(seg, c0);
+                if (c1) take(seg + 1, c1);
+                if (c2) take(seg + 2, c2);
+                if (c3) take(seg + 3, c3);
             }
         }
         __syncthreads();                 // lds_nc is refilled next
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n
                                                     const uint32_t* cand,
                                                     uint32_t* err) {
     tail_priority();
-    __shared__ uint32_t nc[kChainChunk];
+    __shared__ __align__(16) uint32_t nc[kChainChunk];   // read four at a time
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
         const JobView J = view(P.jobs ? P.jobs[job] : P.one);
