@@ -1243,13 +1243,25 @@ __device__ void settle_job(const JobView& J, const ChainWs& ws,
             __syncthreads();
         }
     }
+    // output offsets: each thread sums kRun consecutive segments, one block
+    // scan per kRun x nt segments
+    constexpr uint32_t kRun = 8;
     uint64_t carry = 0;
-    for (uint32_t base = 0; base < J.nseg; base += nt) {
-        const uint32_t k = base + tid;
-        const uint64_t c = k < J.nseg ? M0[k].count : 0;
+    for (uint32_t base = 0; base < J.nseg; base += kRun * nt) {
+        const uint32_t k0 = base + kRun * tid;
+        uint64_t c[kRun], sum = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kRun; r++) {
+            c[r] = k0 + r < J.nseg ? M0[k0 + r].count : 0;
+            sum += c[r];
+        }
         uint64_t total;
-        const uint64_t ex = block_exscan(c, sh, total);
-        if (k < J.nseg) M0[k].out = carry + ex;
+        uint64_t at = carry + block_exscan(sum, sh, total);
+#pragma unroll
+        for (uint32_t r = 0; r < kRun; r++) {
+            if (k0 + r < J.nseg) M0[k0 + r].out = at;
+            at += c[r];
+        }
         carry += total;
     }
     if (tid == 0) *J.n_cuts = carry;
