@@ -31,7 +31,10 @@
  * results (offsets, counts, per-job status) are written on the device in
  * stream order and are valid after the caller synchronises the stream.  The
  * library owns a workspace per (device, stream); it grows only outside
- * stream capture.  Calls on different streams may run concurrently.
+ * stream capture.  A workspace that grows is replaced, not freed: a HIP
+ * graph captured before the growth keeps using the old buffer, which stays
+ * allocated until cdc_release.  Calls on different streams may run
+ * concurrently.
  */
 #ifndef CDC_H
 #define CDC_H
@@ -150,7 +153,9 @@ int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
  */
 int cdc_chunk_each(cdc_job* host_jobs, uint32_t n_jobs, hipStream_t stream);
 
-/* Free every workspace owned by the library (after all work completed). */
+/* Free every workspace owned by the library, including buffers replaced by
+ * growth (after all work completed; graphs captured with library calls must
+ * not be replayed afterwards). */
 void cdc_release(void);
 
 /* Static text for a status code. */
@@ -194,7 +199,9 @@ int cdc_get_tuning(cdc_tuning* t);
  * job count, total bytes, windows, algorithms) in the process: tuning the
  * same shape again only applies the remembered choice.  Synchronises;
  * not for use under capture.  chosen (host, may be null) receives the
- * choice.  Returns CDC_OK, CDC_EINVAL, CDC_ENOMEM or CDC_EHIP.
+ * choice.  Every trial's job statuses are read back: a trial in which a job
+ * ends with a status other than CDC_OK or CDC_EINVAL fails the call with
+ * that status.  Returns CDC_OK, CDC_EINVAL, CDC_ENOMEM or CDC_EHIP.
  */
 int cdc_autotune(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream,
                  uint32_t reps, cdc_tuning* chosen);

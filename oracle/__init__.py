@@ -44,6 +44,12 @@ def _load():
                                      ctypes.c_uint64, ctypes.c_uint64,
                                      ctypes.c_uint64, ctypes.c_void_p,
                                      ctypes.c_uint64]
+        lib.oracle_chunk_many.restype = ctypes.c_int64
+        lib.oracle_chunk_many.argtypes = [ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_next.restype = ctypes.c_uint64
         lib.oracle_next.argtypes = [ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_uint64, ctypes.c_uint64,
@@ -81,3 +87,32 @@ def next_cut(algo, data, w, max_chunk, s):
         raise ValueError("bad arguments")
     return int(_load().oracle_next(algo_id(algo), x.ctypes.data, x.size, w,
                                    max_chunk, s))
+
+
+def chunk_many(algo, data, offsets, lengths, w, max_chunk, base=None):
+    """Chunk every buffer data[offsets[j]:offsets[j]+lengths[j]] on its own.
+
+    Returns (cuts, base, counts): the cuts of buffer j are
+    cuts[base[j]:base[j]+counts[j]].  ``base`` may be given (uint64, one
+    entry per buffer, each leaving room for max_cuts of its buffer)."""
+    x = np.ascontiguousarray(data, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    ln = np.ascontiguousarray(lengths, dtype=np.uint64)
+    assert off.size == ln.size
+    assert x.size == 0 or int((off + ln).max(initial=0)) <= x.size
+    room = np.where(ln > 0, (ln - 1) // np.uint64(w + 1) + 1, 0).astype(np.uint64)
+    if base is None:
+        base = np.zeros(ln.size, np.uint64)
+        if ln.size > 1:
+            np.cumsum(room[:-1], out=base[1:])
+    base = np.ascontiguousarray(base, dtype=np.uint64)
+    size = int((base + room).max(initial=0)) if ln.size else 0
+    cuts = np.zeros(max(1, size), np.uint64)
+    counts = np.zeros(ln.size, np.int64)
+    rc = _load().oracle_chunk_many(algo_id(algo), x.ctypes.data, off.ctypes.data,
+                                   ln.ctypes.data, ln.size, w, max_chunk,
+                                   cuts.ctypes.data, base.ctypes.data,
+                                   counts.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle_chunk_many failed with %d" % rc)
+    return cuts, base, counts

@@ -151,3 +151,23 @@ int64_t oracle_chunk(int algo, const uint8_t* x, uint64_t n, uint64_t w,
     }
     return (int64_t)k;
 }
+
+/*
+ * Many buffers of one byte array, each chunked on its own by the driver of
+ * oracle_chunk: buffer j is x[off[j] .. off[j] + len[j]); its cuts go to
+ * cuts[base[j] ..) (room for (len-1)/(w+1)+1 values) and their number to
+ * counts[j].  Returns 0, or the first negative status of oracle_chunk.
+ */
+int64_t oracle_chunk_many(int algo, const uint8_t* x, const uint64_t* off,
+                          const uint64_t* len, uint64_t njobs, uint64_t w,
+                          uint64_t M, uint64_t* cuts, const uint64_t* base,
+                          int64_t* counts) {
+    for (uint64_t j = 0; j < njobs; j++) {
+        uint64_t room = len[j] == 0 ? 0 : (len[j] - 1) / (w + 1) + 1;
+        int64_t k = oracle_chunk(algo, x + off[j], len[j], w, M,
+                                 cuts + base[j], room);
+        if (k < 0) return k;
+        counts[j] = k;
+    }
+    return 0;
+}

@@ -18,6 +18,20 @@ using Key = std::tuple<int, uint32_t, uint64_t, uint64_t, uint64_t, uint32_t>;
 std::mutex g_tune_mu;
 std::map<Key, cdc_tuning> g_tuned;
 
+// The jobs' statuses after a run: a trial whose batch did not fit the
+// workspace (CDC_ENOMEM on the jobs) fails the tuning instead of being timed
+// as if it had run.  Invalid jobs (CDC_EINVAL) are the caller's and do not.
+int batch_status(const cdc_job* jobs, uint32_t n_jobs, hipStream_t st) {
+    std::vector<cdc_job> h(n_jobs);
+    if (hipMemcpyAsync(h.data(), jobs, n_jobs * sizeof(cdc_job),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return CDC_EHIP;
+    for (const cdc_job& q : h)
+        if (q.status != CDC_OK && q.status != CDC_EINVAL) return q.status;
+    return CDC_OK;
+}
+
 // Average milliseconds of one batch under tuning t (after one untimed run).
 int time_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t st,
                const cdc_tuning& t, uint64_t T, uint32_t wmin, uint32_t mmax,
@@ -36,7 +50,7 @@ int time_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t st,
         hipEventElapsedTime(&f, e0, e1) != hipSuccess)
         return CDC_EHIP;
     *ms = f / reps;
-    return CDC_OK;
+    return batch_status(jobs, n_jobs, st);
 }
 
 }  // namespace

@@ -101,12 +101,11 @@ __device__ JobDesc plan_job(cdc_job* jobs, uint32_t j, const BatchCaps& caps,
         const bool maxp = q.algo == kMaxp;
         d.seg = maxp ? caps.seg_maxp : caps.seg_chain;
         nseg = (q.n + d.seg - 1) / d.seg;
-        const uint64_t span = maxp ? d.seg + kTile : d.seg + q.max_chunk;
-        uint64_t cap = span / ((uint64_t)q.window + 1) + 2;
-        // a job's chains never hold more cuts than the job has
-        cap = min(cap, (q.n + kTile) / ((uint64_t)q.window + 1) + 2);
-        d.cap = (uint32_t)cap;
-        c.v[kSlots] = nseg * cap;
+        // cuts (MAXP: candidates) of a segment lie in (a, a + S + M)
+        // (MAXP: [a, a + S + 1 KiB)) and inside the job, spaced >= w + 1
+        const uint64_t span = min(maxp ? d.seg + kTile : d.seg + q.max_chunk, q.n);
+        d.cap = (uint32_t)(span / ((uint64_t)q.window + 1) + 2);
+        c.v[kSlots] = nseg * d.cap;
         d.blog = maxp ? blog_for(q.window) : 0;
         if (maxp && d.blog) {
             const uint64_t shift = (uintptr_t)q.data & 15;

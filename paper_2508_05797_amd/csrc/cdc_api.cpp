@@ -129,6 +129,11 @@ struct Workspace {
     EventMarks marks;
     void* dev = nullptr;
     size_t cap = 0;
+    // Buffers replaced by a larger one.  A HIP graph captured earlier on the
+    // stream holds their addresses in its kernel arguments, so they stay
+    // allocated until cdc_release (or until the stream's workspace is
+    // dropped); growth is geometric, which bounds what they add up to.
+    std::vector<void*> retired;
     // reservation for batches
     uint32_t res_jobs = 0;
     BatchCaps res_caps{};
@@ -160,12 +165,13 @@ int ensure(Workspace& ws, size_t need, hipStream_t st) {
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) { set_error("hipStreamSynchronize", e); return CDC_EHIP; }
+    size_t cap = align_up(std::max(need, (size_t)1 << 20), (size_t)1 << 20);
     if (ws.dev) {
-        (void)hipFree(ws.dev);
+        cap = std::max(cap, align_up(ws.cap + ws.cap / 2, (size_t)1 << 20));
+        ws.retired.push_back(ws.dev);
         ws.dev = nullptr;
         ws.cap = 0;
     }
-    size_t cap = align_up(std::max(need, (size_t)1 << 20), (size_t)1 << 20);
     e = hipMalloc(&ws.dev, cap);
     if (e != hipSuccess) { set_error("hipMalloc workspace", e); return CDC_ENOMEM; }
     ws.cap = cap;
@@ -197,9 +203,10 @@ uint32_t maxp_blog(uint32_t w) {
 
 // Slots per segment: cuts of a chain through a segment lie in
 // (a, a + S + M) with spacing >= w+1; MAXP candidates lie in [a, a + S + B)
-// with spacing >= w+1.
-uint32_t slots_per_segment(uint32_t algo, uint64_t S, uint32_t w, uint32_t M) {
-    uint64_t span = algo == kMaxp ? S + kTile : S + M;
+// with spacing >= w+1; both also lie inside the job's n bytes.
+uint32_t slots_per_segment(uint32_t algo, uint64_t S, uint32_t w, uint32_t M,
+                           uint64_t n) {
+    const uint64_t span = std::min<uint64_t>(algo == kMaxp ? S + kTile : S + M, n);
     return (uint32_t)(span / ((uint64_t)w + 1) + 2);
 }
 
@@ -248,9 +255,13 @@ ChainWs chain_ws(void* base, const Layout& L) {
 
 // Upper bounds of a batch of at most T bytes in J jobs with windows >= wmin
 // and maximum chunks <= mmax: every job is split into segments of its
-// algorithm's length, and its slots per segment are bounded as in
-// slots_per_segment (the chain and the MAXP bounds are added, since a batch
-// may mix them).
+// algorithm's length S, and its slots per segment are bounded as in
+// slots_per_segment, cap = min(S + extra, n) / (w + 1) + 2 (the chain and
+// the MAXP bounds are added, since a batch may mix them).  Two bounds of
+// the slots hold and the smaller is taken: per item, (T / S + J) items of
+// at most A = (S + extra) / (wmin + 1) + 2 slots; and by length, a job of
+// one segment holds at most n / (wmin + 1) + 2 slots, a job of several
+// (n > S, so fewer than 2n / S segments) at most 2n / S * A.
 BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
     BatchCaps c{};
     c.seg_chain = chain_segment();
@@ -259,10 +270,22 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
     const uint64_t it_chain = T / c.seg_chain + J;
     const uint64_t it_maxp = T / c.seg_maxp + J;
     c.items = std::max(it_chain, it_maxp);
-    c.slots = it_chain * ((c.seg_chain + mmax) / (wmin + 1) + 2) +
-              it_maxp * ((c.seg_maxp + kTile) / (wmin + 1) + 2);
-    const uint32_t blog = maxp_blog((uint32_t)std::min<uint64_t>(wmin, 1u << 30));
-    c.blocks = blog ? (T / kTile + J + 1) * ((uint64_t)kTile >> blog) : 0;
+    auto slot_bound = [&](uint64_t S, uint64_t extra) {
+        const uint64_t A = (S + extra) / (wmin + 1) + 2;
+        const uint64_t per_item = (T / S + J) * A;
+        const uint64_t by_len = T / (wmin + 1) + 2 * J + (2 * T / S + 1) * A;
+        return std::min(per_item, by_len);
+    };
+    c.slots = slot_bound(c.seg_chain, mmax) + slot_bound(c.seg_maxp, kTile);
+    // MAXP block summaries: a job with window w uses blocks of 2^blog(w)
+    // bytes, and none when blog(w) = 0 (w < 15).  Windows below 15 in the
+    // batch say nothing about its MAXP jobs' windows, so the bound takes the
+    // smallest block any MAXP job can use (16 bytes, blog 4) unless wmin
+    // itself allows larger ones.  A job of n bytes starting at an address
+    // with shift s < 16 covers ceil((n + s) / 1 KiB) <= n / 1 KiB + 2 tiles.
+    const uint32_t blog = std::max<uint32_t>(
+        4, maxp_blog((uint32_t)std::min<uint64_t>(wmin, 1u << 30)));
+    c.blocks = (T / kTile + 2 * J + 1) * ((uint64_t)kTile >> blog);
     return c;
 }
 
@@ -293,7 +316,7 @@ size_t single_need(uint32_t algo, uint64_t n, uint32_t w, uint32_t M,
                    uint64_t shift) {
     const uint64_t S = choose_segment(algo, n);
     const uint64_t nseg = (n + S - 1) / S;
-    const uint64_t cap = slots_per_segment(algo, S, w, M);
+    const uint64_t cap = slots_per_segment(algo, S, w, M, n);
     const uint32_t blog = algo == kMaxp ? maxp_blog(w) : 0;
     const uint64_t blocks =
         blog ? (n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> blog) : 0;
@@ -313,6 +336,7 @@ void drop_workspace(hipStream_t st) {
     auto it = g_ws.find({dev, (uintptr_t)st});
     if (it == g_ws.end()) return;
     if (it->second.dev) (void)hipFree(it->second.dev);
+    for (void* r : it->second.retired) (void)hipFree(r);
     it->second.side.destroy();
     for (auto& r : it->second.marks.recs) {
         (void)hipEventDestroy(r.a);
@@ -402,7 +426,7 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
     }
     jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
     jd.item0 = 0;
-    jd.cap = slots_per_segment(jd.algo, jd.seg, jd.w, jd.M);
+    jd.cap = slots_per_segment(jd.algo, jd.seg, jd.w, jd.M, n);
     jd.slot0 = 0;
     jd.blk0 = 0;
     jd.blog = jd.algo == kMaxp ? maxp_blog(jd.w) : 0;
@@ -459,11 +483,12 @@ int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
 void cdc_release(void) {
     std::lock_guard<std::mutex> g(g_mu);
     for (auto& kv : g_ws) {
-        if (kv.second.dev) {
+        if (kv.second.dev || !kv.second.retired.empty()) {
             int cur = 0;
             (void)hipGetDevice(&cur);
             (void)hipSetDevice(kv.first.first);
-            (void)hipFree(kv.second.dev);
+            if (kv.second.dev) (void)hipFree(kv.second.dev);
+            for (void* r : kv.second.retired) (void)hipFree(r);
             kv.second.side.destroy();
             (void)hipSetDevice(cur);
         }

@@ -71,3 +71,20 @@ def test_host_only_entry_points():
     assert L.cdc_get_tuning(None) == -1
     # the serving loop validates before creating streams
     assert L.cdc_serve(None, 0, None, None, None, 0, None, None, None, None) == -1
+
+
+def test_tuning_grid_test_covers_the_autotuner_grid():
+    """The GPU grid test runs exactly the values the autotuner can choose."""
+    import sys
+    src = open(os.path.join(ROOT, "paper_2508_05797_amd", "csrc",
+                            "autotune.cpp")).read()
+
+    def grid(name):
+        m = re.search(name + r"\s*=\s*\{([^}]*)\}", src)
+        return sorted(eval(v.strip()) for v in m.group(1).split(",") if v.strip())
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_gpu_tuning_grid as t
+    assert grid("chain_segs") == sorted(t.CHAIN_SEGS)
+    assert grid("maxp_segs") == sorted(t.MAXP_SEGS)
+    assert grid("waves") == sorted(t.WAVES)

@@ -266,3 +266,90 @@ def test_capture_needs_reservation():
                                            b.n_jobs, ctypes.c_void_p(s.cuda_stream))
     assert rc == -2                      # CDC_ENOMEM
     assert "cdc_reserve" in binding.lib().cdc_last_error().decode()
+
+
+def test_small_window_with_maxp_blocks():
+    """A batch whose smallest window is below 15 (no MAXP block summaries for
+    it) beside MAXP jobs with large windows (which need them): sized without
+    a reservation, every job equals the oracle; also many small misaligned
+    MAXP jobs, each needing up to two partial tiles."""
+    host, offs, sizes = make_files(160, 91, max_len=1 << 20)
+    d = torch.from_numpy(host).cuda()
+    algos = ["ram", "maxp"] * 80
+    windows = [8, 2048] * 80
+    b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        say("case small window + maxp blocks", b.n_jobs)
+        b.run(stream=s)
+    check_batch(b, host, offs, sizes, algos, windows, [65536] * 160)
+    # many small MAXP jobs at odd addresses: 1,500 jobs of 1..2,000 bytes
+    rng = np.random.default_rng(92)
+    k = 1500
+    ln = rng.integers(1, 2000, k)
+    of = np.cumsum(ln + rng.integers(1, 16, k)) - ln
+    assert int(of[-1] + ln[-1]) <= host.size
+    al = ["maxp"] * (k - 1) + ["ram"]
+    wi = [15] * (k - 1) + [3]
+    b2 = binding.Batch(d, of, ln, al, wi, 4000)
+    with torch.cuda.stream(s):
+        say("case many small maxp jobs", b2.n_jobs)
+        b2.run(stream=s)
+    check_batch(b2, host, of, ln, al, wi, [4000] * k)
+    assert binding.device_errors(s) == 0
+
+
+def test_autotune_small_window_mix():
+    """The autotuner on a batch that mixes a window below 15 with MAXP jobs
+    returns a tuning whose batch equals the oracle (its trials used to fail
+    for want of block summaries and were timed anyway)."""
+    host, offs, sizes = make_files(60, 93)
+    d = torch.from_numpy(host).cuda()
+    algos = ["ae", "maxp", "ram"] * 20
+    windows = [5, 2048, 4096] * 20
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+            torch.cuda.synchronize()
+            say("case autotune small window")
+            binding.autotune(b, reps=1, stream=s)
+            b.cuts.fill_(-1)
+            b.run(stream=s)
+        check_batch(b, host, offs, sizes, algos, windows, [65536] * 60)
+    finally:
+        binding.set_tuning()
+
+
+def test_graph_replay_after_workspace_growth():
+    """A batch captured after a reservation, then a much larger call on the
+    same stream (the workspace grows and is replaced): replaying the graph
+    still gives the oracle's offsets, since the buffer the graph was
+    captured with stays allocated."""
+    host, offs, sizes = make_files(100, 95)
+    d = torch.from_numpy(host).cuda()
+    algos = ["ram", "ae", "maxp", "ae_min"] * 25
+    windows = [ALGO_W[a] for a in algos]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        binding.reserve(int(sizes.sum()) + 4096, 128, 2048, 65536, stream=s)
+        b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+        b.run(stream=s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            b.run(stream=s)
+    big = torch.from_numpy(datagen.uniform(96 << 20, 96)).cuda()
+    with torch.cuda.stream(s):
+        say("case growth after capture")
+        c = binding.chunk(big, "ram", 1, 2, stream=s)   # a large workspace
+        assert int(c[-1].item()) == big.numel()
+    for rep in range(2):
+        b.cuts.fill_(-1)
+        b.n_cuts.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("case replay after growth", rep)
+        check_batch(b, host, offs, sizes, algos, windows, [65536] * 100)
+    del big

@@ -113,3 +113,28 @@ def test_serve_rejections():
         exp = oracle.chunk(algos[i], host[o:o + n], int(q["window"]), 65536)
         got = cu[int(q["cut_base"]):int(q["cut_base"]) + int(nc[i])]
         assert np.array_equal(got.astype(np.uint64), exp)
+
+
+def test_serve_small_min_window_with_maxp():
+    """min_window below 15 (no MAXP block summaries for that window) with
+    MAXP requests of larger windows among the requests: the reservation
+    still covers their block summaries, and every request equals the
+    oracle."""
+    host, _ = datagen.mixed_stream(128, 71)            # 8 MiB pool
+    pool = torch.from_numpy(host).cuda()
+    rng = np.random.default_rng(72)
+    k = 400
+    sizes = datagen.lognormal_sizes(k, 73, median=16384, sigma=1.5, lo=1,
+                                    hi=1 << 20)
+    offs = rng.integers(0, host.size - sizes + 1)
+    algos = [["ram", "maxp", "ae"][i] for i in rng.integers(0, 3, k)]
+    windows = np.array([{"ram": 5, "maxp": 2048, "ae": 300}[a] for a in algos])
+    arr = np.cumsum(rng.exponential(1.0 / 30000.0, k))
+    reqs, total = binding.requests(offs, sizes, algos, windows, 65536, arr)
+    say("case serve min window 5 with maxp")
+    cuts, n_cuts, lat, st, stats = binding.serve(pool, reqs, total,
+                                                 budget_bytes=64 << 20,
+                                                 max_batch=64, slots=3,
+                                                 min_window=5)
+    assert stats["rejected"] == 0
+    check_served(host, pool, reqs, cuts, n_cuts, st)

@@ -311,3 +311,19 @@ def test_invalid_params():
         oracle.chunk("ram", x, 0, 10)
     with pytest.raises(ValueError):
         oracle.chunk("ram", x, 5, 5)
+
+
+def test_chunk_many_is_chunk_per_buffer():
+    """The many-buffer driver equals one chunk() per buffer."""
+    rng = np.random.default_rng(23)
+    x = rng.integers(0, 256, 30000).astype(np.uint8)
+    x[5000:12000] = 9
+    offs = rng.integers(0, 20000, 40)
+    lens = rng.integers(0, 10000, 40)
+    lens[:3] = [0, 1, 7]
+    for algo in ["ram", "ae", "maxp", "ae_min"]:
+        cuts, base, cnt = oracle.chunk_many(algo, x, offs, lens, 31, 500)
+        for j in range(40):
+            exp = oracle.chunk(algo, x[offs[j]:offs[j] + lens[j]], 31, 500)
+            got = cuts[int(base[j]):int(base[j]) + int(cnt[j])]
+            assert np.array_equal(got, exp), (algo, j)
