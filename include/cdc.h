@@ -165,6 +165,47 @@ const char* cdc_status_string(int status);
 const char* cdc_last_error(void);
 
 /*
+ * Resumable chunking of a stream that arrives in pieces (an upload: the
+ * paper places chunking on the critical path of incoming data, Section 1).
+ * The pieces, pushed in order, are chunked as one stream: the offsets all
+ * pushes return, concatenated, equal cdc_chunk's offsets on the
+ * concatenated bytes.  A push returns the cuts that the bytes seen so far
+ * decide (for RAM and AE a cut c once c < bytes seen; for MAXP once
+ * c + window <= bytes seen, since a candidate needs its right window); the
+ * open chunk and its bytes (fewer than max_chunk + window) stay in the
+ * object, on the device.  Offsets are absolute positions in the stream.
+ *
+ * cdc_stream_open: a stream object for one chunker and its parameters,
+ *   pieces of at most max_piece bytes, used on `stream` only (every push
+ *   and reset names the same stream).  Allocates its buffers and a
+ *   workspace of its own here (about 3 x (max_chunk + window) bytes plus
+ *   the workspace of a cdc_chunk of max_piece bytes); pushes allocate
+ *   nothing.  Returns CDC_OK, CDC_EINVAL, CDC_ENOMEM or CDC_EHIP.
+ * cdc_stream_max_cuts: room (uint64 entries) a push of len bytes needs in
+ *   cut_offsets.
+ * cdc_stream_push: chunk the next piece (device, len <= max_piece bytes,
+ *   any alignment; read during the push's work only, so it may be reused
+ *   once that work completes).  last != 0 ends the stream: every remaining
+ *   cut is returned (the last one is the stream's length) and further
+ *   pushes are refused until cdc_stream_reset.  cut_offsets (device,
+ *   cdc_stream_max_cuts(len) entries) receives the newly decided offsets,
+ *   n_cuts (device, one uint64) their number.  Asynchronous; nothing is
+ *   read back to the host.  Returns CDC_OK, CDC_EINVAL (bad argument, a
+ *   piece longer than max_piece, another stream, an ended stream) or
+ *   CDC_EHIP.
+ * cdc_stream_reset: start a new stream at offset 0 (on `stream`).
+ * cdc_stream_close: wait for the stream's work and free the object.
+ */
+typedef struct cdc_stream cdc_stream;
+int cdc_stream_open(cdc_algo algo, const cdc_params* p, size_t max_piece,
+                    hipStream_t stream, cdc_stream** out);
+size_t cdc_stream_max_cuts(const cdc_stream* s, size_t len);
+int cdc_stream_push(cdc_stream* s, const uint8_t* piece, size_t len, int last,
+                    uint64_t* cut_offsets, uint64_t* n_cuts, hipStream_t stream);
+int cdc_stream_reset(cdc_stream* s, hipStream_t stream);
+void cdc_stream_close(cdc_stream* s);
+
+/*
  * Tuning knobs.  They change only speed, never the offsets.
  *   chain_segment    bytes per segment of the segment-parallel chain search
  *                    of RAM / AE / AE-Min (16 .. 2^28; 0: 512 KiB);

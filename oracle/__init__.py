@@ -50,6 +50,10 @@ def _load():
                                           ctypes.c_uint64, ctypes.c_uint64,
                                           ctypes.c_uint64, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_pattern_bytes.restype = ctypes.c_int64
+        lib.oracle_pattern_bytes.argtypes = [ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_uint64, ctypes.c_uint64,
+                                             ctypes.c_uint64, ctypes.c_void_p]
         lib.oracle_next.restype = ctypes.c_uint64
         lib.oracle_next.argtypes = [ctypes.c_int, ctypes.c_void_p,
                                     ctypes.c_uint64, ctypes.c_uint64,
@@ -116,3 +120,15 @@ def chunk_many(algo, data, offsets, lengths, w, max_chunk, base=None):
     if rc < 0:
         raise ValueError("oracle_chunk_many failed with %d" % rc)
     return cuts, base, counts
+
+
+def pattern_bytes(algo, data, w, max_chunk):
+    """Bytes the chunker's chain hands to each pattern: (ebs, rs), as
+    oracle_pattern_bytes defines the split of every chunk."""
+    x = np.ascontiguousarray(data, dtype=np.uint8)
+    out = np.zeros(2, np.uint64)
+    k = _load().oracle_pattern_bytes(algo_id(algo), x.ctypes.data, x.size, w,
+                                     max_chunk, out.ctypes.data)
+    if k < 0:
+        raise ValueError("oracle_pattern_bytes failed")
+    return int(out[0]), int(out[1])

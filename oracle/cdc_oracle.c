@@ -171,3 +171,60 @@ int64_t oracle_chunk_many(int algo, const uint8_t* x, const uint64_t* off,
     }
     return 0;
 }
+
+/*
+ * Bytes per pattern (Section 6.3 measures the share of bytes each pattern
+ * handles: RAM spends nearly all of them in the extreme byte search, MAXP in
+ * the range scan).  The chain is the one oracle_chunk computes; each chunk
+ * [s, c) is split by the way Section 4.3 builds the chunker from the two
+ * patterns:
+ *   RAM     the window [s, min(s+w, c)) is searched for its maximum (EBS);
+ *           the bytes after it up to the cut are range-scanned (RS).
+ *   AE      bytes up to and including the final target p (the targets are
+ *           found by range scans) are RS; the bytes after p up to the cut
+ *           are the window whose maximum is compared with p (EBS).
+ *   MAXP    a content cut after the target i = c-1 searches both windows of
+ *           i, 2w bytes (EBS; the right one lies past the cut); the other
+ *           bytes of the chunk, those before the left window and the target
+ *           itself, are range-scanned (RS).  A forced or final chunk is all
+ *           RS.
+ * out[0] += EBS bytes, out[1] += RS bytes.  Returns the number of chunks, or
+ * -1 for invalid parameters.
+ */
+int64_t oracle_pattern_bytes(int algo, const uint8_t* x, uint64_t n, uint64_t w,
+                             uint64_t M, uint64_t* out) {
+    if (!params_ok(w, M) || algo < 0 || algo > 3) return -1;
+    int64_t k = 0;
+    uint64_t s = 0;
+    while (s < n) {
+        uint64_t c = oracle_next(algo, x, n, w, M, s);
+        uint64_t len = c - s;
+        if (algo == ORACLE_ALGO_RAM) {
+            uint64_t win = len < w ? len : w;
+            out[0] += win;
+            out[1] += len - win;
+        } else if (algo == ORACLE_ALGO_AE_MAX || algo == ORACLE_ALGO_AE_MIN) {
+            /* the final target: the last record before the cut */
+            uint64_t p = s;
+            for (uint64_t i = s + 1; i < c; i++) {
+                int better = algo == ORACLE_ALGO_AE_MAX ? x[i] > x[p] : x[i] < x[p];
+                if (better) p = i;
+            }
+            out[1] += p - s + 1;
+            out[0] += c - p - 1;
+        } else {
+            /* a content cut: c-1 is a strict local maximum with full windows
+               and at least w bytes into its chunk */
+            uint64_t i = c - 1;
+            if (i >= s + w && i + w < n && strict_local_max(x, i, w)) {
+                out[0] += 2 * w;
+                out[1] += len - w;
+            } else {
+                out[1] += len;
+            }
+        }
+        k++;
+        s = c;
+    }
+    return k;
+}

@@ -90,6 +90,29 @@ def lib():
                                        ctypes.POINTER(ctypes.c_double), _I]
         L.cdc_check_device_errors.restype = _I
         L.cdc_check_device_errors.argtypes = [_V]
+        L.cdc_stream_open.restype = _I
+        L.cdc_stream_open.argtypes = [_I, ctypes.POINTER(Params), _SZ, _V,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+        L.cdc_stream_max_cuts.restype = _SZ
+        L.cdc_stream_max_cuts.argtypes = [_V, _SZ]
+        L.cdc_stream_push.restype = _I
+        L.cdc_stream_push.argtypes = [_V, _V, _SZ, _I, _V, _V, _V]
+        L.cdc_stream_reset.restype = _I
+        L.cdc_stream_reset.argtypes = [_V, _V]
+        L.cdc_stream_close.restype = None
+        L.cdc_stream_close.argtypes = [_V]
+        L.cdc_fingerprint.restype = _I
+        L.cdc_fingerprint.argtypes = [_V, _SZ, _V, _V, _SZ, _V, _V]
+        L.cdc_dedup_create.restype = _I
+        L.cdc_dedup_create.argtypes = [_U64, _V, ctypes.POINTER(ctypes.c_void_p)]
+        L.cdc_dedup_add.restype = _I
+        L.cdc_dedup_add.argtypes = [_V, _V, _V, _V, _SZ, _V]
+        L.cdc_dedup_stats_get.restype = _I
+        L.cdc_dedup_stats_get.argtypes = [_V, _V, _V]
+        L.cdc_dedup_reset.restype = _I
+        L.cdc_dedup_reset.argtypes = [_V, _V]
+        L.cdc_dedup_destroy.restype = None
+        L.cdc_dedup_destroy.argtypes = [_V]
         L.cdc_serve.restype = _I
         L.cdc_serve.argtypes = [_V, _U64, _V, _V, _V, _U32, _V, _V, _V, _V]
         _lib = L
@@ -331,3 +354,111 @@ def serve(pool, reqs, total_slots, budget_bytes=0, max_batch=1024, slots=4,
 
 def release():
     lib().cdc_release()
+
+
+def fingerprint_into(data, cuts, n_cuts, digests, stream=None):
+    """Enqueue SHA-256 of every chunk of the cut list (int64 device tensors
+    ``cuts`` and ``n_cuts`` as chunk_into fills them) into the uint8 device
+    tensor ``digests`` (32 bytes per slot of ``cuts``)."""
+    assert data.dtype == torch.uint8 and data.is_cuda and data.is_contiguous()
+    assert digests.dtype == torch.uint8 and digests.numel() >= 32 * cuts.numel()
+    _check(lib().cdc_fingerprint(ctypes.c_void_p(data.data_ptr()), data.numel(),
+                                 ctypes.c_void_p(cuts.data_ptr()),
+                                 ctypes.c_void_p(n_cuts.data_ptr()), cuts.numel(),
+                                 ctypes.c_void_p(digests.data_ptr()),
+                                 _stream(stream)))
+
+
+def fingerprint(data, cuts, stream=None):
+    """SHA-256 digests (uint8 device tensor, K x 32) of the chunks that end at
+    the offsets ``cuts`` (an int64 device tensor holding exactly the cuts)."""
+    k = cuts.numel()
+    n_cuts = torch.tensor([k], dtype=torch.int64, device=cuts.device)
+    dg = torch.empty((max(k, 1), 32), dtype=torch.uint8, device=cuts.device)
+    fingerprint_into(data, cuts, n_cuts, dg, stream)
+    return dg[:k]
+
+
+class Dedup:
+    """A device table of distinct chunks (cdc_dedup_*)."""
+
+    FIELDS = ("total_bytes", "chunks", "unique_bytes", "unique_chunks",
+              "collisions", "flags")
+
+    def __init__(self, max_chunks, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().cdc_dedup_create(max_chunks, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def add(self, digests, cuts, n_cuts, stream=None):
+        _check(lib().cdc_dedup_add(self.h, ctypes.c_void_p(digests.data_ptr()),
+                                   ctypes.c_void_p(cuts.data_ptr()),
+                                   ctypes.c_void_p(n_cuts.data_ptr()),
+                                   cuts.numel(), _stream(stream)))
+
+    def stats(self, stream=None):
+        out = (ctypes.c_uint64 * 6)()
+        _check(lib().cdc_dedup_stats_get(self.h, _stream(stream), out))
+        return dict(zip(self.FIELDS, [int(v) for v in out]))
+
+    def reset(self, stream=None):
+        _check(lib().cdc_dedup_reset(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().cdc_dedup_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """A stream chunked in pieces (cdc_stream_*), on one torch stream."""
+
+    def __init__(self, algo, window, max_chunk, max_piece, stream=None):
+        self.torch_stream = stream
+        p = Params(window, max_chunk, 0, 0)
+        h = ctypes.c_void_p()
+        _check(lib().cdc_stream_open(algo_id(algo), ctypes.byref(p), max_piece,
+                                     _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def max_cuts(self, n):
+        return int(lib().cdc_stream_max_cuts(self.h, n))
+
+    def push_into(self, piece, cuts, n_cuts, last=False):
+        """Enqueue a piece (uint8 device tensor); decided offsets go to the
+        int64 device tensors cuts / n_cuts.  Asynchronous."""
+        assert piece.dtype == torch.uint8 and piece.is_cuda and piece.is_contiguous()
+        n = piece.numel()
+        _check(lib().cdc_stream_push(self.h, ctypes.c_void_p(piece.data_ptr() if n else 0),
+                                     n, 1 if last else 0,
+                                     ctypes.c_void_p(cuts.data_ptr()),
+                                     ctypes.c_void_p(n_cuts.data_ptr()),
+                                     _stream(self.torch_stream)))
+
+    def push(self, piece, last=False):
+        """The offsets this piece decides (int64 device tensor; synchronises)."""
+        cuts = torch.empty(self.max_cuts(piece.numel()), dtype=torch.int64,
+                           device=piece.device)
+        nc = torch.empty(1, dtype=torch.int64, device=piece.device)
+        self.push_into(piece, cuts, nc, last)
+        return cuts[:int(nc.item())]
+
+    def reset(self):
+        _check(lib().cdc_stream_reset(self.h, _stream(self.torch_stream)))
+
+    def close(self):
+        if self.h:
+            lib().cdc_stream_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,6 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcdc.so")
 SOURCES = ["chain_kernels.hip", "maxp_kernels.hip", "batch_kernels.hip",
+           "fingerprint_kernels.hip", "fingerprint.cpp", "stream_kernels.hip",
            "cdc_api.cpp", "serve.cpp", "autotune.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

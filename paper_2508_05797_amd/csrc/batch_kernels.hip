@@ -24,12 +24,13 @@ __device__ __forceinline__ uint32_t blog_for(uint32_t w) {
 
 // Counts per job, scanned together: work items per algorithm (so that each
 // algorithm's items are contiguous), cut slots, MAXP blocks.
-constexpr int kNumCounts = 6;
-constexpr int kSlots = 4, kBlocks = 5;
+constexpr int kNumCounts = 7;
+constexpr int kSlots = 4, kBlocks = 5, kTiles = 6;
 
 struct Counts {
     uint64_t v[kNumCounts];
 };
+static_assert(sizeof(Counts) <= 64, "plan_bsum_bytes reserves 64 bytes per block");
 
 __device__ __forceinline__ Counts zero_counts() {
     Counts c;
@@ -107,10 +108,10 @@ __device__ JobDesc plan_job(cdc_job* jobs, uint32_t j, const BatchCaps& caps,
         d.cap = (uint32_t)(span / ((uint64_t)q.window + 1) + 2);
         c.v[kSlots] = nseg * d.cap;
         d.blog = maxp ? blog_for(q.window) : 0;
-        if (maxp && d.blog) {
-            const uint64_t shift = (uintptr_t)q.data & 15;
+        const uint64_t shift = (uintptr_t)q.data & 15;
+        if (maxp && d.blog)
             c.v[kBlocks] = (q.n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> d.blog);
-        }
+        if (!maxp) c.v[kTiles] = (q.n + shift + kTile - 1) / kTile;
         c.v[q.algo] = nseg;
     }
     d.nseg = (uint32_t)nseg;
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(
         d.item0 = d.ok ? (uint32_t)e.v[d.algo] : 0u;
         d.slot0 = e.v[kSlots];
         d.blk0 = e.v[kBlocks];
+        d.idx0 = e.v[kTiles];
         jd[j] = d;
     }
     if (threadIdx.x == 0) bsum[blockIdx.x] = t;
@@ -159,7 +161,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scan(
     if (threadIdx.x == 0) {
         const uint64_t items = carry.v[0] + carry.v[1] + carry.v[2] + carry.v[3];
         const bool over = items > caps.items || carry.v[kSlots] > caps.slots ||
-                          carry.v[kBlocks] > caps.blocks;
+                          carry.v[kBlocks] > caps.blocks || carry.v[kTiles] > caps.tiles;
         ctl[1] = over ? 1u : 0u;
         ctl[0] = over ? 0u : (uint32_t)items;
         uint64_t first = 0;
@@ -193,6 +195,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_items(
         if (valid) d.item0 += ctl[2 + d.algo] + (uint32_t)o.v[d.algo];
         d.slot0 += o.v[kSlots];
         d.blk0 += o.v[kBlocks];
+        d.idx0 += o.v[kTiles];
         if (over) d.ok = 0;
         jd[j] = d;
         jobs[j].status = over ? CDC_ENOMEM : (valid ? CDC_OK : CDC_EINVAL);

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -17,6 +18,7 @@
 
 #include "cdc.h"
 #include "cdc_internal.h"
+#include "stream.h"
 
 namespace cdc {
 namespace {
@@ -143,6 +145,14 @@ struct Workspace {
 std::mutex g_mu;
 std::map<std::pair<int, uintptr_t>, Workspace> g_ws;
 
+}  // namespace
+
+static int batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
+                    uint64_t bytes_hint, bool side, hipStream_t stream,
+                    uint32_t algo_mask);
+
+namespace {
+
 Workspace& workspace_for(hipStream_t st) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -223,16 +233,23 @@ T* at(void* base, size_t off) {
 }
 
 struct Layout {
-    size_t err, meta, spec, fix, rew, bmax, bpos, total;
+    size_t err, idx, meta, spec, fix, rew, bmax, bpos, total;
 };
 
-// Workspace of one job: per item a record and, for RAM / AE, three cut
-// lists (speculative, fix-up, re-walk) of `slots / items` entries each; for
-// MAXP one candidate list and the block summaries.
-Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain) {
+// Tiles (1 KiB, address-aligned) of an n-byte buffer starting at data.
+uint64_t tiles_of(const uint8_t* data, uint64_t n) {
+    return (n + ((uintptr_t)data & 15) + kTile - 1) / kTile;
+}
+
+// Workspace of one job: per item a record and, for RAM / AE, the tile index
+// and three cut lists (speculative, fix-up, re-walk) of `slots / items`
+// entries each; for MAXP one candidate list and the block summaries.
+Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain,
+              uint64_t tiles) {
     Layout L;
     size_t off = 0;
     L.err = off;   off += 256;
+    L.idx = off;   off = align_up(off + (chain ? tiles * 16 : 0), 256);
     L.meta = off;  off = align_up(off + items * sizeof(SegMeta), 256);
     L.spec = off;  off = align_up(off + slots * 4, 256);
     L.fix = off;   off = align_up(off + (chain ? slots * 4 : 0), 256);
@@ -245,6 +262,7 @@ Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain) {
 
 ChainWs chain_ws(void* base, const Layout& L) {
     ChainWs w;
+    w.idx = at<uint4>(base, L.idx);
     w.meta = at<SegMeta>(base, L.meta);
     w.spec = at<uint32_t>(base, L.spec);
     w.fix = at<uint32_t>(base, L.fix);
@@ -286,11 +304,13 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
     const uint32_t blog = std::max<uint32_t>(
         4, maxp_blog((uint32_t)std::min<uint64_t>(wmin, 1u << 30)));
     c.blocks = (T / kTile + 2 * J + 1) * ((uint64_t)kTile >> blog);
+    // tile index of the RAM / AE jobs: ceil((n + shift) / 1 KiB) per job
+    c.tiles = T / kTile + 2 * J + 1;
     return c;
 }
 
 struct BatchLayout {
-    size_t err, nitems, bsum, jd, items, meta, spec, fix, rew, bpos, bmax, total;
+    size_t err, nitems, bsum, jd, items, idx, meta, spec, fix, rew, bpos, bmax, total;
 };
 
 BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
@@ -301,6 +321,7 @@ BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
     L.bsum = off;   off = align_up(off + plan_bsum_bytes(n_jobs), 256);
     L.jd = off;     off = align_up(off + n_jobs * sizeof(JobDesc), 256);
     L.items = off;  off = align_up(off + c.items * sizeof(Item), 256);
+    L.idx = off;    off = align_up(off + c.tiles * 16, 256);
     L.meta = off;   off = align_up(off + c.items * sizeof(SegMeta), 256);
     L.spec = off;   off = align_up(off + c.slots * 4, 256);
     L.fix = off;    off = align_up(off + c.slots * 4, 256);
@@ -320,12 +341,81 @@ size_t single_need(uint32_t algo, uint64_t n, uint32_t w, uint32_t M,
     const uint32_t blog = algo == kMaxp ? maxp_blog(w) : 0;
     const uint64_t blocks =
         blog ? (n + shift + kTile - 1) / kTile * ((uint64_t)kTile >> blog) : 0;
-    return layout(nseg, nseg * cap, blocks, algo != kMaxp).total;
+    return layout(nseg, nseg * cap, blocks, algo != kMaxp,
+                  (n + shift + kTile - 1) / kTile).total;
 }
 
 // Largest grid (in waves) the per-item kernels are launched with; they walk
 // the items grid-stride.
 constexpr uint64_t kMaxGridWaves = 16384;
+
+// The plan of a single-buffer call: validation, its one job and its
+// workspace layout.  wpb receives the waves per workgroup in effect.
+int plan_one(cdc_algo algo, const cdc_params* p, const uint8_t* data, size_t n,
+             uint64_t* cut_offsets, uint64_t* n_cuts, JobDesc& jd, Layout& L,
+             int& wpb) {
+    if (!p || !n_cuts || (n > 0 && (!data || !cut_offsets)) ||
+        p->flags != 0 || p->reserved != 0 ||
+        !params_valid((uint32_t)algo, p->window, p->max_chunk)) {
+        t_last_error = "invalid argument";
+        return CDC_EINVAL;
+    }
+    if (n == 0) return CDC_OK;
+    jd.data = data;
+    jd.n = n;
+    jd.cuts = cut_offsets;
+    jd.n_cuts = n_cuts;
+    jd.status = nullptr;
+    jd.algo = (uint32_t)algo;
+    jd.w = p->window;
+    jd.M = p->max_chunk;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        jd.seg = choose_segment(jd.algo, n);
+        wpb = g_waves_per_block;
+    }
+    jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
+    jd.item0 = 0;
+    jd.cap = slots_per_segment(jd.algo, jd.seg, jd.w, jd.M, n);
+    jd.slot0 = 0;
+    jd.blk0 = 0;
+    jd.idx0 = 0;
+    jd.blog = jd.algo == kMaxp ? maxp_blog(jd.w) : 0;
+    jd.ok = 1;
+    const uint64_t slots = (uint64_t)jd.nseg * jd.cap;
+    const uint64_t blocks = jd.algo == kMaxp ? maxp_blocks(data, n, jd.blog) : 0;
+    L = layout(jd.nseg, slots, blocks, jd.algo != kMaxp, tiles_of(data, n));
+    return CDC_OK;
+}
+
+// n == 0: no offsets, a count of zero.
+int set_empty(uint64_t* n_cuts, hipStream_t st) {
+    hipError_t e = launch_set_u64(n_cuts, 0, st);
+    if (e != hipSuccess) { set_error("launch", e); return CDC_EHIP; }
+    return CDC_OK;
+}
+
+// Enqueue the passes of one planned job over the workspace at `base`
+// (device memory laid out as L).
+int enqueue_one(const JobDesc& jd, const Layout& L, void* base, int wpb,
+                hipStream_t stream, Marks* mk) {
+    Plan P{};
+    P.jobs = nullptr;
+    P.one = jd;
+    P.one_items = jd.nseg;
+    hipError_t e;
+    if (jd.algo == kMaxp) {
+        e = launch_maxp(P, jd.nseg, 1, nullptr, at<SegMeta>(base, L.meta),
+                        at<uint32_t>(base, L.spec), at<uint8_t>(base, L.bmax),
+                        at<int64_t>(base, L.bpos), at<uint32_t>(base, L.err),
+                        wpb, jd.blog != 0, stream, mk);
+    } else {
+        e = launch_ram_ae(P, jd.nseg, 1, nullptr, chain_ws(base, L), wpb,
+                          stream, mk);
+    }
+    if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
+    return CDC_OK;
+}
 
 }  // namespace
 
@@ -398,65 +488,18 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
               size_t n, uint64_t* cut_offsets, uint64_t* n_cuts,
               hipStream_t stream) {
     t_last_error.clear();
-    if (!p || !n_cuts || (n > 0 && (!data || !cut_offsets)) ||
-        p->flags != 0 || p->reserved != 0 ||
-        !params_valid((uint32_t)algo, p->window, p->max_chunk)) {
-        t_last_error = "invalid argument";
-        return CDC_EINVAL;
-    }
-    if (n == 0) {
-        hipError_t e = launch_set_u64(n_cuts, 0, stream);
-        if (e != hipSuccess) { set_error("launch", e); return CDC_EHIP; }
-        return CDC_OK;
-    }
     JobDesc jd{};
-    jd.data = data;
-    jd.n = n;
-    jd.cuts = cut_offsets;
-    jd.n_cuts = n_cuts;
-    jd.status = nullptr;
-    jd.algo = (uint32_t)algo;
-    jd.w = p->window;
-    jd.M = p->max_chunk;
-    int wpb;
-    {
-        std::lock_guard<std::mutex> g(g_mu);
-        jd.seg = choose_segment(jd.algo, n);
-        wpb = g_waves_per_block;
-    }
-    jd.nseg = (uint32_t)((n + jd.seg - 1) / jd.seg);
-    jd.item0 = 0;
-    jd.cap = slots_per_segment(jd.algo, jd.seg, jd.w, jd.M, n);
-    jd.slot0 = 0;
-    jd.blk0 = 0;
-    jd.blog = jd.algo == kMaxp ? maxp_blog(jd.w) : 0;
-    jd.ok = 1;
-    const uint64_t slots = (uint64_t)jd.nseg * jd.cap;
-    const uint64_t blocks = jd.algo == kMaxp ? maxp_blocks(data, n, jd.blog) : 0;
-    const Layout L = layout(jd.nseg, slots, blocks, jd.algo != kMaxp);
-
+    Layout L{};
+    int wpb = 0;
+    int rc = plan_one(algo, p, data, n, cut_offsets, n_cuts, jd, L, wpb);
+    if (rc != CDC_OK || n == 0) return rc == CDC_OK ? set_empty(n_cuts, stream) : rc;
     std::lock_guard<std::mutex> g(g_mu);
     Workspace& ws = workspace_for(stream);
-    int rc = ensure(ws, L.total, stream);
+    rc = ensure(ws, L.total, stream);
     if (rc != CDC_OK) return rc;
-    Plan P{};
-    P.jobs = nullptr;
-    P.one = jd;
-    P.one_items = jd.nseg;
     ws.marks.level = g_profile_level;
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
-    hipError_t e;
-    if (jd.algo == kMaxp) {
-        e = launch_maxp(P, jd.nseg, 1, nullptr, at<SegMeta>(ws.dev, L.meta),
-                        at<uint32_t>(ws.dev, L.spec), at<uint8_t>(ws.dev, L.bmax),
-                        at<int64_t>(ws.dev, L.bpos), at<uint32_t>(ws.dev, L.err),
-                        wpb, jd.blog != 0, stream, mk);
-    } else {
-        e = launch_ram_ae(P, jd.nseg, 1, nullptr, chain_ws(ws.dev, L), wpb,
-                          stream, mk);
-    }
-    if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
-    return CDC_OK;
+    return enqueue_one(jd, L, ws.dev, wpb, stream, mk);
 }
 
 int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
@@ -508,14 +551,22 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
 // With side = false the algorithms run in order on `stream` (for callers
 // that overlap batches on streams of their own).
 int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-                   bool side, hipStream_t stream) {
+                   bool side, hipStream_t stream, uint32_t algo_mask) {
     t_last_error.clear();
     if (!jobs || n_jobs == 0) {
         t_last_error = "invalid argument";
         return CDC_EINVAL;
     }
     std::unique_lock<std::mutex> g(g_mu);
-    Workspace& ws = workspace_for(stream);
+    return batch_on(workspace_for(stream), jobs, n_jobs, bytes_hint, side, stream,
+                    algo_mask);
+}
+
+// The batch on workspace `ws` (g_mu held).  Jobs of algorithms outside
+// algo_mask must not occur (their passes are not enqueued).
+int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
+                  uint64_t bytes_hint, bool side, hipStream_t stream,
+                  uint32_t algo_mask) {
     BatchCaps caps = ws.res_caps;
     if (ws.res_jobs < n_jobs) {
         // No reservation covers this batch: read the descriptors back to size
@@ -564,6 +615,7 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
     ws.marks.level = g_profile_level;
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
     ChainWs cw;
+    cw.idx = at<uint4>(ws.dev, L.idx);
     cw.meta = at<SegMeta>(ws.dev, L.meta);
     cw.spec = at<uint32_t>(ws.dev, L.spec);
     cw.fix = at<uint32_t>(ws.dev, L.fix);
@@ -582,18 +634,20 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
     auto chain = [&](uint32_t algo, hipStream_t st, int part) {
         return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk, part);
     };
+    const bool has_ram = algo_mask & (1u << kRam), has_ae = algo_mask & (1u << kAe);
+    const bool has_min = algo_mask & (1u << kAeMin), has_maxp = algo_mask & (1u << kMaxp);
     if (side && sd.ok) {
         // The streaming passes are enqueued first, so that the host's
         // enqueueing does not hold back their start.
         e = hipEventRecord(sd.fork, stream);
         for (int i = 0; i < kSide && e == hipSuccess; i++)
             e = hipStreamWaitEvent(sd.s[i], sd.fork, 0);
-        if (e == hipSuccess) e = chain(kRam, stream, kPartSpec);
-        if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartSpec);
-        if (e == hipSuccess) e = maxp(sd.s[1]);
-        if (e == hipSuccess) e = chain(kRam, stream, kPartFix | kPartRest);
-        if (e == hipSuccess) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
-        if (e == hipSuccess) e = chain(kAeMin, sd.s[0], kPartAll);
+        if (e == hipSuccess && has_ram) e = chain(kRam, stream, kPartSpec);
+        if (e == hipSuccess && has_ae) e = chain(kAe, sd.s[0], kPartSpec);
+        if (e == hipSuccess && has_maxp) e = maxp(sd.s[1]);
+        if (e == hipSuccess && has_ram) e = chain(kRam, stream, kPartFix | kPartRest);
+        if (e == hipSuccess && has_ae) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
+        if (e == hipSuccess && has_min) e = chain(kAeMin, sd.s[0], kPartAll);
         // the side streams join back even after a failed launch, so that no
         // side work outlives the caller's stream order
         for (int i = 0; i < kSide; i++) {
@@ -601,10 +655,15 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
             if (j == hipSuccess) j = hipStreamWaitEvent(stream, sd.join[i], 0);
             if (e == hipSuccess) e = j;
         }
-        if (e == hipSuccess) e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
+        if (e == hipSuccess && (has_ram || has_ae || has_min))
+            e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
     } else {
-        e = launch_ram_ae(P, grid_waves, n_jobs, nullptr, cw, wpb, stream, mk);
-        if (e == hipSuccess) e = maxp(stream);
+        for (uint32_t a : {kRam, kAe, kAeMin})
+            if (e == hipSuccess && (algo_mask & (1u << a)))
+                e = launch_chain(P, a, grid_waves, n_jobs, nullptr, cw, stream, mk);
+        if (e == hipSuccess && (has_ram || has_ae || has_min))
+            e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
+        if (e == hipSuccess && has_maxp) e = maxp(stream);
     }
     if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
     return CDC_OK;
@@ -674,6 +733,162 @@ int cdc_check_device_errors(hipStream_t stream) {
     if (e == hipSuccess) e = hipMemsetAsync(ws.dev, 0, 4, stream);
     if (e != hipSuccess) { set_error("error word", e); return CDC_EHIP; }
     return (int)flags;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ streams
+
+// A stream chunked in pieces (include/cdc.h, cdc_stream_*): its device
+// state and buffers, and a workspace of its own, reserved at open for
+// batches of one job up to the larger of the largest piece and the staged
+// tail + piece head, so that its batch calls never read descriptors back.
+struct cdc_stream {
+    cdc::StreamDev dev{};
+    void* mem = nullptr;
+    cdc::Workspace ws;
+    uint64_t max_piece = 0;
+    uint64_t staged = 0;       // tail capacity: max_chunk + w + 64
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool finished = false;
+};
+
+namespace {
+
+uint64_t stream_room(uint64_t len, uint64_t w, uint64_t M) {
+    return (len + 2 * M + 2 * w + 128) / (w + 1) + 4;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdc_stream_open(cdc_algo algo, const cdc_params* p, size_t max_piece,
+                    hipStream_t stream, cdc_stream** out) {
+    t_last_error.clear();
+    if (!out || !p || p->flags != 0 || p->reserved != 0 || max_piece == 0 ||
+        !params_valid((uint32_t)algo, p->window, p->max_chunk)) {
+        t_last_error = "invalid argument";
+        return CDC_EINVAL;
+    }
+    *out = nullptr;
+    cdc_stream* S = new (std::nothrow) cdc_stream;
+    if (!S) return CDC_ENOMEM;
+    const uint64_t w = p->window, M = p->max_chunk;
+    S->staged = M + w + 64;
+    S->max_piece = max_piece;
+    S->stream = stream;
+    (void)hipGetDevice(&S->device);
+    const uint64_t stage_cap = (2 * S->staged) / (w + 1) + 4;
+    // state | tail | joined | stage | job
+    const size_t o_tail = 256, o_join = align_up(o_tail + S->staged, 256),
+                 o_stage = align_up(o_join + 2 * S->staged, 256),
+                 o_job = align_up(o_stage + 8 * stage_cap, 256),
+                 total = align_up(o_job + sizeof(cdc_job), 256);
+    if (hipMalloc(&S->mem, total) != hipSuccess) {
+        delete S;
+        t_last_error = "hipMalloc of stream buffers failed";
+        return CDC_ENOMEM;
+    }
+    char* b = static_cast<char*>(S->mem);
+    cdc::StreamDev& D = S->dev;
+    D.st = reinterpret_cast<cdc::StreamState*>(b);
+    D.tail = reinterpret_cast<uint8_t*>(b + o_tail);
+    D.joined = reinterpret_cast<uint8_t*>(b + o_join);
+    D.stage = reinterpret_cast<uint64_t*>(b + o_stage);
+    D.stage_cap = stage_cap;
+    D.job = reinterpret_cast<cdc_job*>(b + o_job);
+    D.tail_cap = S->staged;
+    D.algo = (uint32_t)algo;
+    D.w = p->window;
+    D.M = p->max_chunk;
+    D.lambda = algo == CDC_MAXP ? p->window : 1u;
+    int rc = CDC_OK;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        const uint64_t T = std::max<uint64_t>(max_piece, 2 * S->staged);
+        const BatchCaps caps = batch_caps(T, 1, w, M);
+        rc = ensure(S->ws, batch_layout(caps, 1).total, stream);
+        if (rc == CDC_OK) {
+            S->ws.res_jobs = 1;
+            S->ws.res_caps = caps;
+        }
+    }
+    if (rc == CDC_OK && cdc::launch_stream_reset(D, stream) != hipSuccess) rc = CDC_EHIP;
+    if (rc != CDC_OK) {
+        cdc_stream_close(S);
+        return rc;
+    }
+    *out = S;
+    return CDC_OK;
+}
+
+size_t cdc_stream_max_cuts(const cdc_stream* s, size_t len) {
+    if (!s) return 0;
+    return (size_t)stream_room(len, s->dev.w, s->dev.M);
+}
+
+int cdc_stream_push(cdc_stream* s, const uint8_t* piece, size_t len, int last,
+                    uint64_t* cut_offsets, uint64_t* n_cuts, hipStream_t stream) {
+    t_last_error.clear();
+    if (!s || !n_cuts || !cut_offsets || (len > 0 && !piece) ||
+        len > s->max_piece || stream != s->stream || s->finished) {
+        t_last_error = !s ? "invalid argument"
+                     : s->finished ? "the stream has ended (cdc_stream_reset starts a new one)"
+                     : stream != s->stream ? "pushes must use the stream the stream object was opened on"
+                     : "invalid argument";
+        return CDC_EINVAL;
+    }
+    const cdc::StreamDev& D = s->dev;
+    if (len == 0 && !last) return set_empty(n_cuts, stream);
+    const uint64_t jp = std::min<uint64_t>(len, s->staged);
+    std::lock_guard<std::mutex> g(g_mu);
+    hipError_t e = cdc::launch_stream_join(D, piece, jp, stream);
+    if (e != hipSuccess) { set_error("stream launch", e); return CDC_EHIP; }
+    const uint32_t mask = 1u << D.algo;
+    int rc = batch_on(s->ws, D.job, 1, 2 * s->staged, false, stream, mask);
+    if (rc != CDC_OK) return rc;
+    e = cdc::launch_stream_mid(D, piece, len, jp, last ? 1 : 0, cut_offsets, stream);
+    if (e != hipSuccess) { set_error("stream launch", e); return CDC_EHIP; }
+    if (jp < len) {
+        rc = batch_on(s->ws, D.job, 1, len, false, stream, mask);
+        if (rc != CDC_OK) return rc;
+    }
+    e = cdc::launch_stream_fin(D, piece, len, jp, last ? 1 : 0, cut_offsets, n_cuts,
+                               stream);
+    if (e != hipSuccess) { set_error("stream launch", e); return CDC_EHIP; }
+    if (last) s->finished = true;
+    return CDC_OK;
+}
+
+int cdc_stream_reset(cdc_stream* s, hipStream_t stream) {
+    if (!s || stream != s->stream) return CDC_EINVAL;
+    if (cdc::launch_stream_reset(s->dev, stream) != hipSuccess) return CDC_EHIP;
+    s->finished = false;
+    return CDC_OK;
+}
+
+void cdc_stream_close(cdc_stream* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->device);
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        if (s->ws.dev) (void)hipFree(s->ws.dev);
+        for (void* r : s->ws.retired) (void)hipFree(r);
+        s->ws.side.destroy();
+        for (auto& r : s->ws.marks.recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t ev : s->ws.marks.pool) (void)hipEventDestroy(ev);
+    }
+    if (s->mem) (void)hipFree(s->mem);
+    (void)hipSetDevice(cur);
+    delete s;
 }
 
 }  // extern "C"

@@ -31,6 +31,7 @@ struct JobDesc {
     uint32_t cap;            // cut (or candidate) slots per segment and list
     uint64_t slot0;          // first slot of this job in the slot arrays
     uint64_t blk0;           // first block-summary entry (MAXP)
+    uint64_t idx0;           // first tile-index entry (RAM / AE / AE-Min)
     uint32_t blog;           // log2 of the MAXP block length (0: direct path)
     int32_t ok;              // 1 if the job passed validation
 };
@@ -61,7 +62,7 @@ struct SegMeta {
     uint32_t fms;            // speculative index the fix-up chain continues from, or kNone
     uint32_t count;          // cuts of the current resolution
     uint32_t npieces;
-    uint32_t cval;           // RAM: 0x100 | v when every byte of the segment is v, else 0
+    uint32_t reads;          // tiles whose bytes the walkers of this item read
     Piece pieces[3];
 };
 
@@ -85,7 +86,7 @@ enum : uint32_t { kErrOverflow = 1u };
 
 // Capacity of a batch workspace and the planning constants.
 struct BatchCaps {
-    uint64_t items, slots, blocks;
+    uint64_t items, slots, blocks, tiles;
     uint64_t seg_chain, seg_maxp;
     uint64_t max_chunk_limit;
 };
@@ -99,6 +100,7 @@ struct Marks {
 // Host-side launch sequences (defined with the kernels).
 // Workspace of the RAM / AE passes.
 struct ChainWs {
+    uint4* idx;              // tile index entries (job's idx0 on)
     SegMeta* meta;           // per item
     uint32_t* spec;          // speculative cuts, cap per item (job slots)
     uint32_t* fix;           // fix-up cuts, cap per item
@@ -138,7 +140,7 @@ hipError_t launch_plan(cdc_job* jobs, uint32_t n_jobs, const BatchCaps& caps,
                        JobDesc* jd, Item* items, uint32_t* ctl, void* bsum,
                        hipStream_t st);
 constexpr size_t plan_bsum_bytes(uint64_t n_jobs) {
-    return (size_t)((n_jobs + 1023) / 1024) * 48;
+    return (size_t)((n_jobs + 1023) / 1024) * 64;   // one Counts (7 words) per block
 }
 hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 
@@ -147,10 +149,11 @@ hipError_t launch_clear_u32(uint32_t* p, size_t count, hipStream_t st);
 void drop_workspace(hipStream_t st);
 
 // cdc_chunk_batch with the batch's total length known to the caller (0: not
-// known; the length only sizes the launch grids), and the choice of running
+// known; the length only sizes the launch grids), the choice of running
 // the algorithms side by side on the workspace's own streams (side) or in
-// order on `stream`.
+// order on `stream`, and the algorithms the batch can contain (bit a of
+// algo_mask for algorithm a; the passes of the others are not enqueued).
 int batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-              bool side, hipStream_t stream);
+              bool side, hipStream_t stream, uint32_t algo_mask = 0xFu);
 
 }  // namespace cdc

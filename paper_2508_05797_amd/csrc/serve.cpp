@@ -104,13 +104,19 @@ public:
             j.status = 0;
         }
         uint64_t total = 0;
-        for (size_t k = 0; k < batch.size(); k++) total += s.host[k].n;
+        uint32_t mask = 0;
+        for (size_t k = 0; k < batch.size(); k++) {
+            total += s.host[k].n;
+            mask |= 1u << (s.host[k].algo & 3u);
+        }
         const size_t bytes = batch.size() * sizeof(cdc_job);
         if (hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice,
                            s.stream) != hipSuccess)
             return false;
         // batches overlap across slots; within one, the algorithms run in order
-        if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, false, s.stream) != CDC_OK)
+        // only the passes of the algorithms the batch holds
+        if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, false, s.stream,
+                           mask) != CDC_OK)
             return false;
         if (hipMemcpyAsync(s.host, s.dev, bytes, hipMemcpyDeviceToHost,
                            s.stream) != hipSuccess ||

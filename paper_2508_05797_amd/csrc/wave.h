@@ -173,7 +173,7 @@ struct JobView {
     const uint8_t* data;
     int64_t n, w, M, seg;
     uint32_t algo, nseg, item0, cap, ok, blog;
-    uint64_t slot0, blk0;
+    uint64_t slot0, blk0, idx0;
     uint64_t* cuts;
     uint64_t* n_cuts;
 };
@@ -193,6 +193,7 @@ __device__ __forceinline__ JobView view(const JobDesc& J) {
     v.blog = uni(J.blog);
     v.slot0 = (uint64_t)uni64((int64_t)J.slot0);
     v.blk0 = (uint64_t)uni64((int64_t)J.blk0);
+    v.idx0 = (uint64_t)uni64((int64_t)J.idx0);
     v.cuts = (uint64_t*)uni64((int64_t)J.cuts);
     v.n_cuts = (uint64_t*)uni64((int64_t)J.n_cuts);
     return v;

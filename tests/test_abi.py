@@ -88,3 +88,32 @@ def test_tuning_grid_test_covers_the_autotuner_grid():
     assert grid("chain_segs") == sorted(t.CHAIN_SEGS)
     assert grid("maxp_segs") == sorted(t.MAXP_SEGS)
     assert grid("waves") == sorted(t.WAVES)
+
+
+def test_sha256_constants_follow_their_definition():
+    """The SHA-256 round constants and initial state in the fingerprint
+    kernels are the first 32 bits of the fractional parts of the cube roots
+    of the first 64 primes and of the square roots of the first 8 primes
+    (FIPS 180-4, 4.2.2 and 5.3.3), recomputed here to 60 digits."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    src = open(os.path.join(ROOT, "paper_2508_05797_amd", "csrc",
+                            "fingerprint_kernels.hip")).read()
+
+    def table(name):
+        m = re.search(name + r"\[\d+\]\s*=\s*\{([^}]*)\}", src)
+        return [int(v.strip().rstrip("u"), 16) for v in m.group(1).split(",")]
+
+    primes = []
+    n = 2
+    while len(primes) < 64:
+        if all(n % p for p in primes):
+            primes.append(n)
+        n += 1
+
+    def frac_bits(p, r):
+        x = Decimal(p) ** (Decimal(1) / Decimal(r))
+        return int((x - int(x)) * (1 << 32))
+
+    assert table("kSha256K") == [frac_bits(p, 3) for p in primes]
+    assert table("kSha256H0") == [frac_bits(p, 2) for p in primes[:8]]

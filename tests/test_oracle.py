@@ -327,3 +327,45 @@ def test_chunk_many_is_chunk_per_buffer():
             exp = oracle.chunk(algo, x[offs[j]:offs[j] + lens[j]], 31, 500)
             got = cuts[int(base[j]):int(base[j]) + int(cnt[j])]
             assert np.array_equal(got, exp), (algo, j)
+
+
+def test_pattern_bytes_exact_cases():
+    """Bytes per pattern on inputs whose chains are known in closed form."""
+    w, M = 50, 400
+    # constant bytes: every chunk is w+1 long; RAM and AE search the w-byte
+    # window (EBS) and take the one byte after it (RS); MAXP never cuts
+    n = 20 * (w + 1)
+    x = np.full(n, 9, np.uint8)
+    for a in ("ram", "ae", "ae_min"):
+        assert oracle.pattern_bytes(a, x, w, M) == (20 * w, 20)
+    assert oracle.pattern_bytes("maxp", x, w, M) == (0, n)
+    # spikes every 150 bytes from 60 on: MAXP cuts right after each spike
+    # whose right window is complete; such a chunk searches both windows
+    x = np.zeros(1000, np.uint8)
+    spikes = list(range(60, 1000, 150))
+    x[spikes] = 255
+    cuts = oracle.chunk("maxp", x, w, M)
+    ebs = 2 * w * sum(1 for q in spikes if q + w < 1000)
+    assert oracle.pattern_bytes("maxp", x, w, M) == (ebs, 1000 + w * (ebs // (2 * w)) - ebs)
+    assert [int(c) for c in cuts[:-1]] == [q + 1 for q in spikes if q + w < 1000]
+    # strictly increasing bytes (AE-Max): every byte is a new target, so the
+    # whole chunk is range-scanned up to each forced cut
+    x = np.arange(256, dtype=np.uint8)
+    assert oracle.pattern_bytes("ae", x, 20, 64) == (0, 256)
+    # RAM where the window does not fit the last chunk: all of it is window
+    x = np.full(3 * (w + 1) + 10, 4, np.uint8)
+    assert oracle.pattern_bytes("ram", x, w, M) == (3 * w + 10, 3)
+
+
+def test_pattern_bytes_ram_uniform_closed_form():
+    """RAM on uniform bytes: the window (w bytes) almost surely holds a 255,
+    and the scan after it stops at the first 255, about 256 bytes later
+    (a geometric wait), so the window's share is w / (w + 256)."""
+    x = np.random.default_rng(12).integers(0, 256, 48 << 20).astype(np.uint8)
+    for w in (1024, 4096):
+        e, r = oracle.pattern_bytes("ram", x, w, 1 << 20)
+        share = e / (e + r)
+        chunks = x.size / (w + 256)
+        # the scan's mean has a standard error of about 256 / sqrt(chunks)
+        tol = 4 * 256 / chunks ** 0.5 * w / (w + 256) ** 2
+        assert abs(share - w / (w + 256)) < tol, (w, share)
