@@ -97,6 +97,29 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
               hipStream_t stream);
 
 /*
+ * cdc_chunk for callers that cannot allocate device memory: code under HIP
+ * graph capture that has no reservation, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, semantics and results as
+ * cdc_chunk, but the library's working memory is a fixed 32 MiB array per
+ * device inside the library (held from load until the process ends)
+ * instead of a per-stream workspace: nothing is allocated, no workspace is
+ * created, and no event is recorded (profiling does not apply).
+ * Limit: the call's workspace (per segment of the chain search a record and
+ * three cut lists of about (segment + max_chunk) / (window + 1) slots; for
+ * MAXP, block summaries of the input and a candidate list) must fit the
+ * 32 MiB; with the built-in tuning that covers, for example, about 8 GiB
+ * for RAM or AE at window 4096 and about 2.5 GiB for MAXP at window 2048.
+ * Larger requests are refused with CDC_ENOMEM before anything is enqueued,
+ * cdc_last_error() stating the bytes needed.  All calls on one device share
+ * the array: calls that can overlap on the device (on different streams,
+ * or from different host threads) race and must not be issued; calls in
+ * one stream's order are safe.  Returns as cdc_chunk.
+ */
+int cdc_chunk_noalloc(cdc_algo algo, const cdc_params* p, const uint8_t* data,
+                      size_t n, uint64_t* cut_offsets, uint64_t* n_cuts,
+                      hipStream_t stream);
+
+/*
  * One job of a batch.  data (device, n bytes), cut_offsets (device, room for
  * cdc_max_cuts entries) and n_cuts (device, one uint64) are owned by the
  * caller; algo/window/max_chunk as for cdc_chunk.  status is written by the
@@ -266,8 +289,9 @@ int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
 
 /*
  * Diagnostic: synchronise `stream`, return and clear the sticky flags the
- * kernels raised on it (bit 0: a chain exceeded its planned slot bound,
- * which indicates a library bug; 0 when nothing was flagged), or CDC_EHIP.
+ * kernels raised on it, and those raised by cdc_chunk_noalloc calls on the
+ * current device (bit 0: a chain exceeded its planned slot bound, which
+ * indicates a library bug; 0 when nothing was flagged), or CDC_EHIP.
  */
 int cdc_check_device_errors(hipStream_t stream);
 

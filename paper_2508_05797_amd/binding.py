@@ -64,6 +64,8 @@ def lib():
         L.cdc_max_cuts.argtypes = [ctypes.POINTER(Params), _SZ]
         L.cdc_chunk.restype = _I
         L.cdc_chunk.argtypes = [_I, ctypes.POINTER(Params), _V, _SZ, _V, _V, _V]
+        L.cdc_chunk_noalloc.restype = _I
+        L.cdc_chunk_noalloc.argtypes = [_I, ctypes.POINTER(Params), _V, _SZ, _V, _V, _V]
         L.cdc_chunk_batch.restype = _I
         L.cdc_chunk_batch.argtypes = [_V, _U32, _V]
         L.cdc_reserve.restype = _I
@@ -149,6 +151,19 @@ def chunk_into(data, algo, window, max_chunk, cuts, n_cuts, stream=None):
                            ctypes.c_void_p(data.data_ptr() if n else 0), n,
                            ctypes.c_void_p(cuts.data_ptr()),
                            ctypes.c_void_p(n_cuts.data_ptr()), _stream(stream)))
+
+
+def chunk_noalloc_into(data, algo, window, max_chunk, cuts, n_cuts, stream=None):
+    """As chunk_into, through cdc_chunk_noalloc (the library's fixed scratch
+    array instead of a per-stream workspace; nothing is allocated)."""
+    assert data.dtype == torch.uint8 and data.is_cuda and data.is_contiguous()
+    n = data.numel()
+    p = Params(window, max_chunk, 0, 0)
+    _check(lib().cdc_chunk_noalloc(algo_id(algo), ctypes.byref(p),
+                                   ctypes.c_void_p(data.data_ptr() if n else 0), n,
+                                   ctypes.c_void_p(cuts.data_ptr()),
+                                   ctypes.c_void_p(n_cuts.data_ptr()),
+                                   _stream(stream)))
 
 
 def chunk(data, algo, window, max_chunk, stream=None):

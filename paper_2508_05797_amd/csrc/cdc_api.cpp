@@ -417,6 +417,40 @@ int enqueue_one(const JobDesc& jd, const Layout& L, void* base, int wpb,
     return CDC_OK;
 }
 
+// Scratch of the entry point that allocates nothing (cdc_chunk_noalloc):
+// one fixed array per device, in the code object, zero at load.  In host
+// code `scratch` names a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, with that device current, and only
+// that address is ever passed to kernels.  Its first word collects the
+// kernels' sticky error flags (cleared by cdc_check_device_errors).
+constexpr size_t kScratchBytes = 32u << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (looked up on its first use).
+int scratch_base(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_error("hipGetDevice", e); return CDC_EHIP; }
+    if (dev < 0 || dev >= kMaxDevices) {
+        t_last_error = "cdc_chunk_noalloc: device index out of range";
+        return CDC_ENOTSUP;
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch)", e);
+            return CDC_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CDC_OK;
+}
+
 }  // namespace
 
 void drop_workspace(hipStream_t st) {
@@ -500,6 +534,29 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
     ws.marks.level = g_profile_level;
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
     return enqueue_one(jd, L, ws.dev, wpb, stream, mk);
+}
+
+int cdc_chunk_noalloc(cdc_algo algo, const cdc_params* p, const uint8_t* data,
+                      size_t n, uint64_t* cut_offsets, uint64_t* n_cuts,
+                      hipStream_t stream) {
+    t_last_error.clear();
+    JobDesc jd{};
+    Layout L{};
+    int wpb = 0;
+    int rc = plan_one(algo, p, data, n, cut_offsets, n_cuts, jd, L, wpb);
+    if (rc != CDC_OK || n == 0) return rc == CDC_OK ? set_empty(n_cuts, stream) : rc;
+    if (L.total > kScratchBytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf,
+                 "cdc_chunk_noalloc: this call needs %zu bytes of scratch, more "
+                 "than the %zu the entry point has", L.total, kScratchBytes);
+        t_last_error = buf;
+        return CDC_ENOMEM;
+    }
+    void* base = nullptr;
+    rc = scratch_base(&base);
+    if (rc != CDC_OK) return rc;
+    return enqueue_one(jd, L, base, wpb, stream, nullptr);
 }
 
 int cdc_reserve(hipStream_t stream, size_t max_total_bytes, uint32_t max_jobs,
@@ -726,12 +783,20 @@ int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
 int cdc_check_device_errors(hipStream_t stream) {
     std::lock_guard<std::mutex> g(g_mu);
     Workspace& ws = workspace_for(stream);
-    if (!ws.dev) return 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    void* words[2] = {ws.dev, dev >= 0 && dev < kMaxDevices ? g_scratch_ptr[dev] : nullptr};
     uint32_t flags = 0;
-    hipError_t e = hipMemcpyAsync(&flags, ws.dev, 4, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ws.dev, 0, 4, stream);
-    if (e != hipSuccess) { set_error("error word", e); return CDC_EHIP; }
+    for (void* w : words) {
+        if (!w) continue;
+        uint32_t f = 0;
+        hipError_t e = hipMemcpyAsync(&f, w, 4, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e == hipSuccess) e = hipMemsetAsync(w, 0, 4, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) { set_error("error word", e); return CDC_EHIP; }
+        flags |= f;
+    }
     return (int)flags;
 }
 

@@ -90,6 +90,26 @@ def test_tuning_grid_test_covers_the_autotuner_grid():
     assert grid("waves") == sorted(t.WAVES)
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcdc.so not built")
+def test_noalloc_refuses_beyond_scratch_without_a_device():
+    """cdc_chunk_noalloc checks its request against its fixed scratch before
+    touching a device: a request that does not fit is refused with
+    CDC_ENOMEM and a message naming the bytes it would need."""
+    from paper_2508_05797_amd import binding
+    L = binding.lib()
+    p = binding.Params(1, 2, 0, 0)
+    fake = ctypes.c_void_p(0x1000)
+    rc = L.cdc_chunk_noalloc(0, ctypes.byref(p), fake, 1 << 30, fake, fake,
+                             ctypes.c_void_p(0))
+    assert rc == -2
+    msg = L.cdc_last_error().decode()
+    assert "scratch" in msg and str(32 << 20) in msg
+    # invalid parameters are refused first
+    bad = binding.Params(0, 2, 0, 0)
+    assert L.cdc_chunk_noalloc(0, ctypes.byref(bad), fake, 10, fake, fake,
+                               ctypes.c_void_p(0)) == -1
+
+
 def test_sha256_constants_follow_their_definition():
     """The SHA-256 round constants and initial state in the fingerprint
     kernels are the first 32 bits of the fractional parts of the cube roots

@@ -1,0 +1,66 @@
+"""cdc_chunk_noalloc (GPU): the entry point that allocates nothing gives
+exactly cdc_chunk's offsets, on two calls in a row whose second input is
+smaller (the shared scratch array keeps the first call's contents), for
+every chunker; a request beyond its scratch is refused before any work."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2508_05797_amd import binding, datagen
+
+pytestmark = pytest.mark.gpu
+
+W = {"ram": 4096, "ae": 4096, "maxp": 2048, "ae_min": 300}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def noalloc(d, algo, w, M):
+    n = d.numel()
+    cuts = torch.full((max(1, binding.max_cuts(n, w)),), -1, dtype=torch.int64,
+                      device=d.device)
+    nc = torch.full((1,), -1, dtype=torch.int64, device=d.device)
+    binding.chunk_noalloc_into(d, algo, w, M, cuts, nc)
+    return cuts[:int(nc.item())]
+
+
+@pytest.mark.parametrize("algo", ["ram", "ae", "maxp", "ae_min"])
+def test_noalloc_equals_chunk(algo):
+    assert torch.cuda.is_available()
+    x, _ = datagen.mixed_stream(160, 81)               # 10 MiB
+    x[3 << 20:(3 << 20) + 700000] = 17
+    big = torch.from_numpy(x).cuda()
+    small = big[12345:12345 + (3 << 20) + 777]         # smaller, unaligned
+    w = W[algo]
+    for tag, d, host in (("first", big, x), ("second, smaller", small,
+                                              x[12345:12345 + (3 << 20) + 777])):
+        say("case noalloc", algo, tag, d.numel())
+        got = noalloc(d, algo, w, 65536)
+        ref = binding.chunk(d, algo, w, 65536)
+        assert torch.equal(got, ref), (algo, tag)
+        exp = oracle.chunk(algo, host, w, 65536)
+        assert np.array_equal(got.cpu().numpy().astype(np.uint64), exp), (algo, tag)
+    assert binding.device_errors() == 0
+
+
+def test_noalloc_empty_and_refused():
+    d = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    assert noalloc(d[:0], "ram", 16, 100).numel() == 0
+    p = binding.Params(1, 2, 0, 0)
+    n = 1 << 30                                       # w=1: far beyond 32 MiB
+    cuts = torch.empty(1, dtype=torch.int64, device="cuda")
+    nc = torch.full((1,), -7, dtype=torch.int64, device="cuda")
+    rc = binding.lib().cdc_chunk_noalloc(0, ctypes.byref(p),
+                                         ctypes.c_void_p(d.data_ptr()), n,
+                                         ctypes.c_void_p(cuts.data_ptr()),
+                                         ctypes.c_void_p(nc.data_ptr()),
+                                         ctypes.c_void_p(0))
+    assert rc == -2                                   # CDC_ENOMEM
+    assert b"scratch" in binding.lib().cdc_last_error()
+    torch.cuda.synchronize()
+    assert int(nc.item()) == -7                       # nothing was enqueued
