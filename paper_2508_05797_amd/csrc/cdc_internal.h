@@ -63,6 +63,7 @@ struct SegMeta {
     uint32_t count;          // cuts of the current resolution
     uint32_t npieces;
     uint32_t reads;          // tiles whose bytes the walkers of this item read
+    uint32_t claim;          // settling pass that holds this segment
     Piece pieces[3];
 };
 

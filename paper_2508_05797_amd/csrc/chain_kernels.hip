@@ -26,11 +26,10 @@
 
 namespace cdc {
 
-// Positions at the walker interface are 32-bit offsets from the segment
+// Positions inside the chain engine are 32-bit offsets from the segment
 // start (segments and chunks are at most 2^28 bytes, so every position a
-// walker of the segment reaches fits); the walker itself works in job
-// offsets.
-constexpr int32_t kRelClamp = 0x7FFFF000;
+// walker of the segment reaches fits), which keeps the walkers' state and
+// compares on the scalar unit.
 
 // ------------------------------------------------------------ index pass
 
@@ -52,6 +51,7 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
     const int64_t t1 = (b + src.shift + kTile - 1) >> 10;
     uint4* out = idx + J.idx0;
     const int64_t nw = blockDim.x / kWave, wv = uni(threadIdx.x / kWave);
+    uint32_t guess = 255;
     for (int64_t t = t0 + wv * kIdxAhead; t < t1; t += nw * kIdxAhead) {
         uint4 v[kIdxAhead];
 #pragma unroll
@@ -60,7 +60,10 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
 #pragma unroll
         for (int i = 0; i < kIdxAhead; i++) {
             if (t + i < t1) {
-                const uint4 e = summarize_tile<INV>(v[i], src.tile_pos(t + i), J.n, slots);
+                const int64_t tp = src.tile_pos(t + i);
+                const bool whole = tp >= 0 && tp + kTile <= J.n;
+                const uint4 e = summarize_tile<INV>(v[i], tp, J.n, whole, slots, guess);
+                guess = ie_max(e.x);
                 if (lane_id() == 0) out[t + i] = e;
             }
         }
@@ -69,44 +72,74 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
 
 // ------------------------------------------------------------ next()
 
-// One chain step from chunk start s (job offset): the chunk's exclusive end.
+// One chain step from chunk start s (offset from the walker's base): the
+// chunk's exclusive end.
 template <bool RAM, bool INV>
-__device__ __forceinline__ int64_t chain_next(IdxWalker<INV>& X, int64_t s,
-                                              int64_t w, int64_t M) {
-    const int64_t L = min(X.n, s + M);
+__device__ __forceinline__ int32_t chain_next(IdxWalker<INV>& X, int32_t s,
+                                              int32_t w, int32_t M) {
+    const int32_t L = s + M < X.n ? s + M : X.n;   // (no overflow: s, M < 2^29)
     if constexpr (RAM) {
         if (s + w >= L) return L;                  // the window does not fit
         const uint32_t T = X.range_max(s, s + w);
         if (T == 0) return s + w + 1;              // every byte is >= 0
-        const int64_t j = X.first_geq(s + w, L, T);
+        const int32_t j = X.first_geq(s + w, L, T);
         return j >= 0 ? j + 1 : L;
     } else {
-        int64_t p = s;
+        // the first occurrence q of the largest byte V of [s, s + w] is
+        // where the target goes; from there only the window's new part,
+        // past what was searched, can hold a greater byte
+        int32_t hi = min(s + w + 1, L);
+        uint32_t V = X.range_max(s, hi);
+        int32_t p = V == 0 ? s : X.first_geq(s, hi, V);
         for (;;) {
-            const int64_t hi = min(p + w + 1, L);  // [p, p + w] before the limit
-            const uint32_t V = X.range_max(p, hi);
-            const int64_t q = V == 0 ? p : X.first_geq(p, hi, V);
-            if (q == p) return p + w < L ? p + w + 1 : L;
-            p = q;
+            // a target of 255 cannot be exceeded: it is the last one
+            if (V == 255u) break;
+            const int32_t nhi = min(p + w + 1, L);
+            if (nhi <= hi) break;                  // nothing new: p is final
+            const uint32_t m2 = X.range_max(hi, nhi);
+            if (m2 <= V) break;                    // nothing greater after p
+            p = X.first_geq(hi, nhi, m2);
+            V = m2;
+            hi = nhi;
         }
+        return p + w < L ? p + w + 1 : L;
     }
 }
 
 // Walk from chunk start `start` (relative to base); emit(c) gets each chunk
 // end (relative) and returns true to stop.  The walk also stops at the
-// job's end.  Returns the number of tiles whose bytes were read.
+// job's end.  Inside a run of whole tiles of one value, every chunk whose
+// w + 1 bytes lie in the run is exactly w + 1 long for RAM (its window's
+// maximum is the value and the next byte equals it) and for AE (nothing in
+// its window exceeds the first byte), so those ends follow without queries.
+// Returns the tiles whose bytes the two patterns read (extreme byte search
+// in the low half, range scan in the high half).
 template <bool RAM, bool INV, class Emit>
 __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
                          int32_t start, Emit& emit) {
     IdxWalker<INV> X;
-    X.init(J, ws.idx + J.idx0, ws.err);
-    int64_t s = base + start;
-    while (s < J.n) {
-        const int64_t c = chain_next<RAM, INV>(X, s, J.w, J.M);
-        if (emit((int32_t)min(c - base, (int64_t)kRelClamp))) break;
+    X.init(J, ws.idx + J.idx0, base);
+    const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
+    int32_t s = start;
+    bool stop = false;
+    while (s < X.n && !stop) {
+        const int32_t re = X.const_run_end(s, w);
+        if (re >= 0) {
+            while (s + w <= re - 1) {
+                const int32_t c = s + w + 1;
+                if (emit(c)) {
+                    stop = true;
+                    break;
+                }
+                s = c;
+            }
+            continue;
+        }
+        const int32_t c = chain_next<RAM, INV>(X, s, w, M);
+        if (emit(c)) break;
         s = c;
     }
-    return X.fallbacks;
+    return min(X.reads_ebs, 0xFFFFu) | (min(X.reads_rs, 0xFFFFu) << 16);
 }
 
 // ------------------------------------------------------------ lists
@@ -344,6 +377,7 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
 // the item table grid-stride.
 constexpr int kChainThreads = 256;
 constexpr int kChainWaves = kChainThreads / kWave;
+constexpr uint32_t kSettleList = 1024;   // flagged segments settled per pass
 
 template <bool ONE, class F>
 __device__ __forceinline__ void for_items(const Plan& P, uint32_t want, F&& f) {
@@ -445,64 +479,72 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
     return ex;
 }
 
-// Settle one RAM / AE job with the whole block: segments whose entry is not
-// their predecessor's resolved exit are resolved again, in order, by wave 0
-// (after the parallel rounds there are rarely any, and a walk over the index
-// is short); then output offsets are assigned.
+// Settle one RAM / AE job with the whole block.  A segment is flagged when
+// its entry is not its predecessor's resolved exit.  Each pass takes the
+// heads of the runs of flagged segments (a flagged segment whose predecessor
+// is not flagged: its entry is final) side by side, one wave each; a wave
+// resolves its head again and goes on into the following segments, in
+// order, while the exit it found changes the next segment's entry, up to
+// the next head.  Passes repeat until nothing is flagged (a head reached
+// from before it changes its entry, and is flagged again); each pass
+// settles every head, so a job's chain is walked once in order, by as many
+// waves as it has independent stretches.  Then output offsets are
+// assigned.
 template <bool RAM, bool INV>
 __device__ void settle_job(const JobView& J, const ChainWs& ws, uint64_t* sh,
                            uint32_t* flagged, uint32_t& n_flagged) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    const uint32_t nwaves = nt / kWave, wv = uni(tid / kWave);
     SegMeta* M0 = ws.meta + J.item0;
-    for (uint32_t base = 1; base < J.nseg; base += nt) {
-        if (tid == 0) n_flagged = 0;
-        __syncthreads();
-        const uint32_t k = base + tid;
-        if (k < J.nseg && M0[k].entry != M0[k - 1].rexit) {
-            const uint32_t slot = atomicAdd(&n_flagged, 1u);
-            flagged[slot] = k;
+    auto is_flagged = [&](uint32_t k) {
+        return k >= 1 && k < J.nseg && M0[k].entry != M0[k - 1].rexit;
+    };
+    for (uint32_t pass = 1;; pass++) {
+        if (tid == 0) {
+            n_flagged = 0;
+            flagged[kSettleList] = ~0u;         // the lowest head
         }
         __syncthreads();
-        const uint32_t cnt = n_flagged;
-        if (cnt > 0) {
-            if (tid == 0) {              // in segment order
-                for (uint32_t i = 1; i < cnt; i++) {
-                    const uint32_t v = flagged[i];
-                    uint32_t j = i;
-                    while (j > 0 && flagged[j - 1] > v) {
-                        flagged[j] = flagged[j - 1];
-                        j--;
+        uint32_t any = 0;
+        for (uint32_t k = 1 + tid; k < J.nseg; k += nt) {
+            if (is_flagged(k)) {
+                any = 1;
+                if (!is_flagged(k - 1)) {        // the head of a run
+                    atomicMin(&flagged[kSettleList], k);
+                    const uint32_t slot = atomicAdd(&n_flagged, 1u);
+                    if (slot < kSettleList) {
+                        flagged[slot] = k;
+                        M0[k].claim = pass;
                     }
-                    flagged[j] = v;
                 }
             }
-            __syncthreads();
-            if (tid < kWave) {
-                // Walk the flagged segments in order; a segment resolved
-                // again can change its successor's entry (also past this
-                // block's range), which is then resolved right away.
-                uint32_t li = 0;
-                uint32_t k2 = uni(flagged[0]);
-                int64_t prev = uni64((int64_t)M0[k2 - 1].rexit);
-                for (;;) {
-                    int64_t h = uni64((int64_t)M0[k2].rexit);
-                    if (prev != uni64((int64_t)M0[k2].entry))
-                        h = resolve_from<RAM, INV>(J, k2, J.item0 + k2, prev,
-                                                   false, ws);
-                    while (li < cnt && uni(flagged[li]) <= k2) li++;
-                    const uint32_t nxt = k2 + 1;
-                    if (nxt < J.nseg && uni64((int64_t)M0[nxt].entry) != h) {
-                        k2 = nxt;
-                        prev = h;
-                        continue;
-                    }
-                    if (li == cnt) break;
-                    k2 = uni(flagged[li]);
-                    prev = uni64((int64_t)M0[k2 - 1].rexit);
-                }
-            }
-            __syncthreads();
         }
+        any = __syncthreads_or(any);
+        if (!any) break;
+        if (tid == 0 && n_flagged > kSettleList) {
+            // more heads than the list holds: the lowest one (its entry is
+            // final) is always among those settled, so every pass progresses
+            const uint32_t lo = flagged[kSettleList];
+            flagged[0] = lo;
+            M0[lo].claim = pass;
+        }
+        __syncthreads();
+        const uint32_t cnt = min(n_flagged, kSettleList);
+        for (uint32_t i = wv; i < cnt; i += nwaves) {
+            uint32_t k2 = uni(flagged[i]);
+            int64_t prev = uni64((int64_t)M0[k2 - 1].rexit);
+            for (;;) {
+                const int64_t h = resolve_from<RAM, INV>(J, k2, J.item0 + k2, prev,
+                                                         false, ws);
+                const uint32_t nxt = k2 + 1;
+                if (nxt >= J.nseg || uni(M0[nxt].claim) == pass ||
+                    uni64((int64_t)M0[nxt].entry) == h)
+                    break;
+                k2 = nxt;
+                prev = h;
+            }
+        }
+        __syncthreads();
     }
     // output offsets: each thread sums kRun consecutive segments, one block
     // scan per kRun x nt segments
@@ -535,7 +577,7 @@ __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
                                                  ChainWs ws) {
     tail_priority();
     __shared__ uint64_t sh[256];
-    __shared__ uint32_t flagged[256];
+    __shared__ uint32_t flagged[kSettleList + 1];
     __shared__ uint32_t n_flagged;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {

@@ -7,18 +7,18 @@
 // its bytes equal m, whether all of them do, and the offsets of the first
 // seven that do.  One streaming pass writes the summaries (16 bytes per
 // KiB); a walker then keeps 64 consecutive summaries in the lanes of one
-// wave (64 KiB of input per page) and takes a chunk step with a few ballots
-// and lane reads:
+// wave (64 KiB of input per page) and answers each query with one
+// lane-parallel pass over the page and a ballot:
 //   * the largest byte of [lo, hi): the maxima of the tiles the range covers
 //     whole, plus each partly covered end tile's maximum when one of its
 //     stored positions of m falls in the range;
 //   * the first byte >= T in [lo, hi): the first tile with m >= T, and in
 //     it the first stored position of m in the range when m == T (every
 //     byte >= T then equals m).
-// Where the summary cannot decide (a partly covered tile whose maximum lies
-// outside the range and matters; m > T in the scanned tile; more than seven
-// positions of m, the ones needed not stored) the walker reads that one
-// tile's bytes and answers from them.  Answers are exact either way.
+// Where the summary cannot decide (a partly covered end tile whose maximum
+// lies outside the range and matters; m > T in a scanned tile; more than
+// seven positions of m, the ones needed not stored) the walker reads that
+// one tile's bytes and answers from them.  Answers are exact either way.
 //
 // Bytes outside the job are absent: they are not counted in m, in the
 // count or the positions (a tile of a job's first or last granules holds
@@ -30,69 +30,106 @@
 namespace cdc {
 
 constexpr int kIdxPos = 7;                 // stored positions per tile
+constexpr uint32_t kNoPos = 0xFFFFu;
 
 // entry dword 0: m | cnt << 8 (saturated at 127) | all_m << 15 | pos0 << 16;
-// dwords 1..3: pos1..pos6, 16 bits each (0xFFFF: none)
+// dwords 1..3: pos1..pos6, 16 bits each (kNoPos: none); positions ascend.
 __device__ __forceinline__ uint32_t ie_max(uint32_t x) { return x & 0xFFu; }
 __device__ __forceinline__ uint32_t ie_cnt(uint32_t x) { return (x >> 8) & 0x7Fu; }
 __device__ __forceinline__ bool ie_all(uint32_t x) { return (x >> 15) & 1u; }
-__device__ __forceinline__ uint32_t ie_pos(const uint4& e, int k) {
-    const uint32_t d = k == 0 ? e.x : k <= 2 ? e.y : k <= 4 ? e.z : e.w;
-    return (k & 1) ? (d & 0xFFFFu) : (d >> 16);
+
+// ------------------------------------------------------------ summaries
+
+// High bit of each byte of d set iff that byte is zero.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t d) {
+    const uint32_t t = (d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    return ~(t | d | 0x7F7F7F7Fu);
 }
 
-// 16-bit mask of the lane's bytes equal to v (v <= 255).
-__device__ __forceinline__ uint32_t eq_mask16(const uint4& q, uint32_t v) {
-    const uint32_t r = v * 0x01010101u;
-    const uint32_t d[4] = {q.x ^ r, q.y ^ r, q.z ^ r, q.w ^ r};
-    uint32_t m = 0;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        // high bit of each byte set iff that byte of d is zero
-        uint32_t t = (d[i] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-        t = ~(t | d[i] | 0x7F7F7F7Fu);
-        // gather the four high bits into bits 4i..4i+3
-        const uint32_t g = ((t >> 7) & 1u) | ((t >> 14) & 2u) | ((t >> 21) & 4u) |
-                           ((t >> 28) & 8u);
-        m |= g << (4 * i);
-    }
-    return m;
-}
-
-// Bits [a, b) of a 16-bit mask.
-__device__ __forceinline__ uint32_t bit_range16(int a, int b) {
-    return b <= a ? 0u : ((0xFFFFu >> (16 - (b - a))) << a) & 0xFFFFu;
-}
-
-// Summary of tile t of the job (one wave; every lane calls it alike).
-// slots: eight 16-bit LDS words of this wave.
+// Summary of one tile whose bytes are raw (every lane calls it alike).
+// tp: job position of the tile's first byte; whole: every byte of the tile
+// belongs to the job (uniform).  slots: eight 16-bit LDS words of this wave.
+// guess: a likely maximum (the previous tile's); when no lane holds more
+// and one holds it, the wave reduction is skipped.
 template <bool INV>
-__device__ __forceinline__ uint4 summarize_tile(const uint4& raw, int64_t tp,
-                                                int64_t n, uint16_t* slots) {
-    const int64_t lp = tp + 16 * (int64_t)lane_id();
-    const int a = (int)min(max(-lp, (int64_t)0), (int64_t)16);
-    const int b = (int)min(max(n - lp, (int64_t)0), (int64_t)16);
-    const uint4 v = (a > 0 || b < 16) ? keep_bytes(raw, a, b) : raw;
-    const uint32_t m = uni(wave_max(lane_max16(v)));
-    const uint32_t eq = eq_mask16(v, m) & bit_range16(a, b);
-    const uint32_t c = (uint32_t)__builtin_popcount(eq);
-    const uint32_t incl = seg_sum<kWave>(c);
-    const uint32_t total = uni((uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1));
-    const uint32_t ex = incl - c;
-    // bytes of the job in this tile
+__device__ __forceinline__ uint4 summarize_tile(uint4 v, int64_t tp, int64_t n,
+                                                bool whole, uint16_t* slots,
+                                                uint32_t guess) {
+    int a = 0, b = 16;
+    if (!whole) {                                  // a tile at the job's ends
+        const int64_t lp = tp + 16 * (int64_t)lane_id();
+        a = (int)min(max(-lp, (int64_t)0), (int64_t)16);
+        b = (int)min(max(n - lp, (int64_t)0), (int64_t)16);
+        v = keep_bytes(v, a, b);
+    }
+    const uint32_t lm = lane_max16(v);
+    uint32_t m = guess;
+    if (__ballot(lm > guess) || !__ballot(lm == guess)) m = uni(wave_max(lm));
+    const uint32_t r = m * 0x01010101u;
+    uint32_t z0 = zero_bytes(v.x ^ r), z1 = zero_bytes(v.y ^ r);
+    uint32_t z2 = zero_bytes(v.z ^ r), z3 = zero_bytes(v.w ^ r);
+    if (!whole) {                                  // bytes outside the job
+        const uint32_t keep = 0xFFFFu >> (16 - (b - a)) << a;   // bits [a, b)
+        const uint32_t k = b > a ? keep : 0u;
+        auto spread = [](uint32_t nib) {           // 4 bits -> high bits of 4 bytes
+            return ((nib & 1u) << 7) | ((nib & 2u) << 14) | ((nib & 4u) << 21) |
+                   ((nib & 8u) << 28);
+        };
+        z0 &= spread(k & 15u);
+        z1 &= spread((k >> 4) & 15u);
+        z2 &= spread((k >> 8) & 15u);
+        z3 &= spread((k >> 12) & 15u);
+    }
+    const uint32_t c = __builtin_popcount(z0) + __builtin_popcount(z1) +
+                       __builtin_popcount(z2) + __builtin_popcount(z3);
     const int64_t lo = max(tp, (int64_t)0), hi = min(tp + kTile, n);
     const uint32_t in_tile = hi > lo ? (uint32_t)(hi - lo) : 0u;
-    if (lane_id() < 8) slots[lane_id()] = 0xFFFFu;
-    __builtin_amdgcn_wave_barrier();
-    uint32_t rest = eq;
-    for (uint32_t r = ex; rest && r < (uint32_t)kIdxPos; r++) {
-        const int bit = __builtin_ctz(rest);
-        rest &= rest - 1;
-        slots[r] = (uint16_t)(16 * lane_id() + bit);
+    uint32_t total;
+    uint4 p;
+    const uint64_t many = __ballot(c >= 2);
+    if (whole && many == ~0ull && !__ballot(c != 16)) {
+        // one value throughout: its first seven positions are 0..6
+        total = kTile;
+        p = make_uint4(0x00010000u, 0x00030002u, 0x00050004u, 0xFFFF0006u);
+    } else if (!many) {
+        // at most one byte equal to m per lane: ranks by counting lanes
+        const uint64_t has = __ballot(c != 0);
+        total = (uint32_t)__builtin_popcountll(has);
+        const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(has >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)has, 0u));
+        if (lane_id() < 8) slots[lane_id()] = (uint16_t)kNoPos;
+        __builtin_amdgcn_wave_barrier();
+        if (c && rk < (uint32_t)kIdxPos) {
+            const uint64_t lo2 = ((uint64_t)z1 << 32) | z0, hi2 = ((uint64_t)z3 << 32) | z2;
+            const int i = lo2 ? (__builtin_ctzll(lo2) >> 3) : 8 + (__builtin_ctzll(hi2) >> 3);
+            slots[rk] = (uint16_t)(16 * lane_id() + i);
+        }
+        __builtin_amdgcn_wave_barrier();
+        p = *(const uint4*)slots;                  // eight halves
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        const uint32_t incl = seg_sum<kWave>(c);
+        total = uni((uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1));
+        const uint32_t ex = incl - c;
+        if (lane_id() < 8) slots[lane_id()] = (uint16_t)kNoPos;
+        __builtin_amdgcn_wave_barrier();
+        if (c && ex < (uint32_t)kIdxPos) {
+            // this lane's bytes equal to m, in order, into the free ranks
+            uint64_t bits = ((uint64_t)z1 << 32) | z0;
+            uint32_t rk = ex;
+            for (int h = 0; h < 2 && rk < (uint32_t)kIdxPos; h++) {
+                while (bits && rk < (uint32_t)kIdxPos) {
+                    const int i = __builtin_ctzll(bits) >> 3;     // byte index
+                    bits &= bits - 1;
+                    slots[rk++] = (uint16_t)(16 * lane_id() + 8 * h + i);
+                }
+                bits = ((uint64_t)z3 << 32) | z2;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        p = *(const uint4*)slots;                  // eight halves
+        __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
-    const uint4 p = *(const uint4*)slots;   // 8 halves, little-endian pairs
-    __builtin_amdgcn_wave_barrier();
     uint4 e;
     e.x = m | (min(total, 127u) << 8) | ((in_tile > 0 && total == in_tile) ? 0x8000u : 0u) |
           (p.x << 16);
@@ -103,185 +140,201 @@ __device__ __forceinline__ uint4 summarize_tile(const uint4& raw, int64_t tp,
     return e;
 }
 
-// A walker over the job's index: the page of 64 summaries from tile p0 in
-// this lane's registers (and the following page loaded ahead).  Positions
-// are job offsets.
+// ------------------------------------------------------------ walker
+
+// A walker over a job's index from segment base `base` on.  Its positions
+// are 32-bit offsets from base and its tiles are counted from the tile that
+// holds base (tile k starts at offset 1024 k - ph), so that its state and
+// compares stay on the scalar unit.  The page is the 64 summaries from tile
+// p0 on, one per lane.
 template <bool INV>
 struct IdxWalker {
+    const uint4* idx;     // summary of tile k at idx[k]
     Source src;
-    const uint4* idx;
-    int64_t ntiles, n;
-    int64_t p0, p1;       // first tile of the page / of the page loaded ahead
-    uint4 e, e1;
-    uint32_t* err;
-    uint32_t fallbacks;   // tiles whose bytes were read
+    int64_t t0;           // the job's tile number of tile 0
+    int32_t ph;           // offset of base inside tile 0
+    int32_t n;            // job length from base (clamped)
+    int32_t ntiles;       // tiles from tile 0 to the job's end (clamped)
+    int32_t p0;           // first tile of the page (far below 0 before the first load)
+    uint4 e;              // this lane's summary (tile p0 + lane)
+    uint32_t reads_ebs, reads_rs;   // tiles whose bytes each pattern read
 
-    __device__ void init(const JobView& J, const uint4* index, uint32_t* e_) {
+    __device__ void init(const JobView& J, const uint4* job_idx, int64_t base) {
         src.init(J.data, (uint64_t)J.n);
-        n = J.n;
-        idx = index;
-        ntiles = (int64_t)((uint64_t)(J.n + src.shift + kTile - 1) >> 10);
-        p0 = p1 = -1;
-        err = e_;
-        fallbacks = 0;
+        t0 = (base + src.shift) >> 10;
+        ph = (int32_t)((base + src.shift) & (kTile - 1));
+        idx = job_idx + t0;
+        const int64_t nrel = J.n - base;
+        n = (int32_t)min(nrel, (int64_t)0x7FFFF000);
+        const int64_t nt = (int64_t)((uint64_t)(J.n + src.shift + kTile - 1) >> 10) - t0;
+        ntiles = (int32_t)min(nt, (int64_t)0x7FFFFFFF);
+        p0 = INT32_MIN / 2;                      // no page yet
+        reads_ebs = reads_rs = 0;
     }
-    __device__ __forceinline__ uint4 load_page(int64_t t) const {
-        const int64_t k = t + lane_id();
-        uint4 r = make_uint4(0, 0, 0, 0);
-        if (k < ntiles) r = idx[k];
-        return r;
-    }
-    // make tile t part of the current page
-    __device__ __forceinline__ void need(int64_t t) {
-        if (t >= p0 && t < p0 + kWave && p0 >= 0) return;
-        if (p1 >= 0 && t >= p1 && t < p1 + kWave) {
-            p0 = p1;
-            e = e1;
-        } else {
-            p0 = t;
-            e = load_page(t);
-        }
-        p1 = p0 + kWave;
-        if (p1 < ntiles)
-            e1 = load_page(p1);
-        else
-            p1 = -1;
-    }
-    __device__ __forceinline__ uint4 entry(int64_t t) {
-        need(t);
-        const int l = (int)(t - p0);
-        return make_uint4((uint32_t)__builtin_amdgcn_readlane((int)e.x, l),
-                          (uint32_t)__builtin_amdgcn_readlane((int)e.y, l),
-                          (uint32_t)__builtin_amdgcn_readlane((int)e.z, l),
-                          (uint32_t)__builtin_amdgcn_readlane((int)e.w, l));
-    }
-    __device__ __forceinline__ int64_t tile_of(int64_t pos) const {
-        return (pos + src.shift) >> 10;
-    }
-    __device__ __forceinline__ int64_t tile_start(int64_t t) const {
-        return t * kTile - src.shift;
+    __device__ __forceinline__ int32_t tile(int32_t pos) const { return (pos + ph) >> 10; }
+    __device__ __forceinline__ int32_t tstart(int32_t k) const { return (k << 10) - ph; }
+    // make tile k part of the page (a page starts at the first tile needed)
+    __device__ __forceinline__ void need(int32_t k) {
+        if ((uint32_t)(k - p0) < (uint32_t)kWave) return;   // p0 starts far below
+        p0 = k;
+        const int32_t t = k + (int32_t)lane_id();
+        e = t < ntiles ? idx[t] : make_uint4(0, 0, 0, 0);
     }
 
-    // Largest m over tiles [ta, tb) (ta < tb).
-    __device__ uint32_t tiles_max(int64_t ta, int64_t tb) {
-        uint32_t M = 0;
-        for (int64_t t = ta; t < tb && M < 255;) {
-            need(t);
-            const int64_t k0 = t - p0, k1 = min(tb - p0, (int64_t)kWave);
-            const int64_t l = lane_id();
-            const uint32_t mv = (l >= k0 && l < k1) ? ie_max(e.x) : 0u;
-            M = max(M, uni(wave_max(mv)));
-            t = p0 + k1;
-        }
-        return M;
-    }
-    // First tile in [ta, tb) with m >= T, or -1.
-    __device__ int64_t first_tile_geq(int64_t ta, int64_t tb, uint32_t T) {
-        for (int64_t t = ta; t < tb;) {
-            need(t);
-            const int64_t k0 = t - p0, k1 = min(tb - p0, (int64_t)kWave);
-            const int64_t l = lane_id();
-            const uint64_t b = __ballot(l >= k0 && l < k1 && ie_max(e.x) >= T);
-            if (b) return p0 + __builtin_ctzll(b);
-            t = p0 + k1;
-        }
-        return -1;
-    }
-
-    // ---- the bytes of one tile (when the summary cannot decide)
-    __device__ __forceinline__ uint4 tile_bytes(int64_t t, int64_t lo, int64_t hi) {
-        fallbacks++;
-        uint4 v = src.template load<INV>(t);
-        // keep the bytes of [lo, hi) only
-        const int64_t lp = tile_start(t) + 16 * (int64_t)lane_id();
-        const int a = (int)min(max(lo - lp, (int64_t)0), (int64_t)16);
-        const int b = (int)min(max(hi - lp, (int64_t)0), (int64_t)16);
+    // ---- a tile's bytes (where the summary cannot decide)
+    __device__ __forceinline__ uint4 tile_bytes(int32_t k, int32_t lo, int32_t hi) {
+        uint4 v = src.template load<INV>(t0 + k);
+        const int32_t lp = tstart(k) + 16 * (int32_t)lane_id();
+        const int a = min(max(lo - lp, 0), 16), b = min(max(hi - lp, 0), 16);
         return keep_bytes(v, a, b);
     }
-    // exact largest byte of [lo, hi) inside tile t
-    __device__ uint32_t bytes_max(int64_t t, int64_t lo, int64_t hi) {
-        const uint4 v = tile_bytes(t, lo, hi);
-        return uni(wave_max(lane_max16(v)));
+    __device__ uint32_t bytes_max(int32_t k, int32_t lo, int32_t hi) {
+        reads_ebs++;
+        return uni(wave_max(lane_max16(tile_bytes(k, lo, hi))));
     }
-    // first position in [lo, hi) inside tile t with a byte >= T (1..255), or -1
-    __device__ int64_t bytes_first_geq(int64_t t, int64_t lo, int64_t hi, uint32_t T) {
-        const uint4 v = tile_bytes(t, lo, hi);   // bytes outside are 0 < T
-        const uint32_t lm = lane_max16(v);
-        uint64_t ball = __ballot(lm >= T);
+    // first offset in [lo, hi) within tile k with a byte >= T (1..255), or -1
+    __device__ int32_t bytes_first_geq(int32_t k, int32_t lo, int32_t hi, uint32_t T) {
+        reads_rs++;
+        const uint4 v = tile_bytes(k, lo, hi);         // bytes outside are 0 < T
+        const uint64_t ball = __ballot(lane_max16(v) >= T);
         if (!ball) return -1;
         const int f = __builtin_ctzll(ball);
-        const uint32_t q0 = (uint32_t)__builtin_amdgcn_readlane((int)v.x, f);
-        const uint32_t q1 = (uint32_t)__builtin_amdgcn_readlane((int)v.y, f);
-        const uint32_t q2 = (uint32_t)__builtin_amdgcn_readlane((int)v.z, f);
-        const uint32_t q3 = (uint32_t)__builtin_amdgcn_readlane((int)v.w, f);
-        const uint32_t d[4] = {q0, q1, q2, q3};
+        const uint32_t d[4] = {(uint32_t)__builtin_amdgcn_readlane((int)v.x, f),
+                               (uint32_t)__builtin_amdgcn_readlane((int)v.y, f),
+                               (uint32_t)__builtin_amdgcn_readlane((int)v.z, f),
+                               (uint32_t)__builtin_amdgcn_readlane((int)v.w, f)};
+        int i = 0;
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
-            const uint32_t by = (d[i >> 2] >> (8 * (i & 3))) & 0xFFu;
-            if (by >= T) return tile_start(t) + 16 * f + i;
+        for (int j = 15; j >= 0; j--)
+            if (((d[j >> 2] >> (8 * (j & 3))) & 0xFFu) >= T) i = j;
+        return tstart(k) + 16 * f + i;
+    }
+
+    // ---- one tile's summary, read out to scalar registers
+
+    // Lanes [l0, l1] of the page as a mask (0 <= l0 <= l1 <= 63).
+    __device__ __forceinline__ static uint64_t lanes(int32_t l0, int32_t l1) {
+        const uint64_t hi = l1 >= 63 ? ~0ull : ((2ull << l1) - 1ull);
+        return hi & (~0ull << l0);
+    }
+    __device__ __forceinline__ uint32_t xword(int32_t l) const {
+        return (uint32_t)__builtin_amdgcn_readlane((int)e.x, l);
+    }
+    // First stored position of the tile's maximum in offsets [a, b), from the
+    // summary of lane l whose first word is x; returns kNoPos when none is
+    // stored there, and sets *undecided when the tile may still hold one
+    // there (more than seven positions, all stored ones before a).
+    __device__ uint32_t first_pos(int32_t l, uint32_t x, uint32_t a, uint32_t b,
+                                  bool& undecided) const {
+        undecided = false;
+        const uint32_t p0 = x >> 16;
+        if (p0 >= a) return p0 < b ? p0 : kNoPos;     // the first one overall
+        const uint32_t cnt = ie_cnt(x);
+        if (cnt <= 1) return kNoPos;
+        const uint32_t y = (uint32_t)__builtin_amdgcn_readlane((int)e.y, l);
+        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)e.z, l);
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)e.w, l);
+        const uint32_t ps[6] = {y & 0xFFFFu, y >> 16, z & 0xFFFFu, z >> 16,
+                                w & 0xFFFFu, w >> 16};
+        const uint32_t k_n = min(cnt, (uint32_t)kIdxPos) - 1;
+        for (uint32_t k = 0; k < k_n; k++) {
+            const uint32_t p = ps[k];
+            if (p >= a) return p < b ? p : kNoPos;
         }
-        return -1;   // not reached: the lane maximum was >= T
+        undecided = cnt > (uint32_t)kIdxPos;          // all seven before a
+        return kNoPos;
+    }
+
+    // End (exclusive) of the run of bytes equal to the byte at s that
+    // consists of whole tiles of one value from s's tile on (or, at the job's
+    // end, the job's last bytes), when that run reaches past s + w; else -1.
+    __device__ int32_t const_run_end(int32_t s, int32_t w) {
+        const int32_t k0 = tile(s);
+        need(k0);
+        const uint32_t x = xword(k0 - p0);
+        if (!ie_all(x)) return -1;
+        const uint32_t v = ie_max(x);
+        for (int32_t k = k0;;) {
+            need(k);
+            const uint32_t me = e.x;
+            const uint64_t brk = __ballot(!ie_all(me) || ie_max(me) != v) &
+                                 (~0ull << (k - p0));
+            if (brk) {
+                const int32_t re = min(tstart(p0 + __builtin_ctzll(brk)), n);
+                return re - 1 >= s + w ? re : -1;
+            }
+            k = p0 + kWave;
+            if (k >= ntiles) {
+                const int32_t re = n;
+                return re - 1 >= s + w ? re : -1;
+            }
+        }
     }
 
     // ---- the two patterns, exact
 
-    // Largest byte in [lo, hi) (lo < hi): extreme byte search.
-    __device__ uint32_t range_max(int64_t lo, int64_t hi) {
-        const int64_t ta = tile_of(lo), tb = tile_of(hi - 1);
-        if (ta == tb) return part_max(ta, lo, hi, 0);
-        uint32_t M = ta + 1 < tb ? tiles_max(ta + 1, tb) : 0u;
-        if (M >= 255) return M;
-        M = part_max(ta, lo, tile_start(ta) + kTile, M);
-        if (M >= 255) return M;
-        return part_max(tb, tile_start(tb), hi, M);
-    }
-    // max(M, largest byte of [lo, hi) inside tile t)
-    __device__ uint32_t part_max(int64_t t, int64_t lo, int64_t hi, uint32_t M) {
-        const uint4 q = entry(t);
-        const uint32_t m = ie_max(q.x);
+    // max(M, largest byte of [lo, hi) inside end tile k)
+    __device__ uint32_t end_max(int32_t k, int32_t lo, int32_t hi, uint32_t M) {
+        need(k);
+        const int32_t l = k - p0;
+        const uint32_t x = xword(l);
+        const uint32_t m = ie_max(x);
         if (m <= M) return M;
-        const int64_t ts = tile_start(t);
-        if (ie_all(q.x) || (lo <= max(ts, (int64_t)0) && hi >= min(ts + kTile, n)))
-            return m;                                 // the whole tile's bytes
-        const int64_t a = lo - ts, b = hi - ts;
-        const uint32_t cnt = ie_cnt(q.x);
-        const int k_n = (int)min(cnt, (uint32_t)kIdxPos);
-        for (int k = 0; k < k_n; k++) {
-            const int64_t p = ie_pos(q, k);
-            if (p >= b) break;                        // sorted: none in range
-            if (p >= a) return m;
-        }
-        return max(M, bytes_max(t, lo, hi));
+        if (ie_all(x)) return m;
+        const int32_t ts = tstart(k);
+        bool und;
+        if (first_pos(l, x, (uint32_t)(lo - ts), (uint32_t)(hi - ts), und) != kNoPos)
+            return m;
+        return max(M, bytes_max(k, lo, hi));          // its maximum lies outside
     }
+
+    // Largest byte in [lo, hi) (0 <= lo < hi <= n): extreme byte search.
+    __device__ uint32_t range_max(int32_t lo, int32_t hi) {
+        const int32_t ka = tile(lo), kb = tile(hi - 1);
+        if (ka == kb) return end_max(ka, lo, hi, 0);
+        uint32_t M = 0;
+        for (int32_t k = ka + 1; k < kb;) {            // tiles covered whole
+            need(k);
+            const int32_t last = min(kb - 1, p0 + kWave - 1);
+            const uint64_t msk = lanes(k - p0, last - p0);
+            const uint32_t m = ie_max(e.x);
+            if (__ballot(m == 255u) & msk) return 255u;
+            const int32_t l = (int32_t)lane_id();
+            M = max(M, uni(wave_max(((msk >> l) & 1ull) ? m : 0u)));
+            k = last + 1;
+        }
+        M = end_max(ka, lo, tstart(ka) + kTile, M);
+        if (M < 255u) M = end_max(kb, tstart(kb), hi, M);
+        return M;
+    }
+
     // First j in [lo, hi) with byte >= T (1 <= T <= 255), or -1: range scan.
-    __device__ int64_t first_geq(int64_t lo, int64_t hi, uint32_t T) {
+    __device__ int32_t first_geq(int32_t lo, int32_t hi, uint32_t T) {
         if (lo >= hi) return -1;
-        const int64_t tl = tile_of(hi - 1);
-        for (int64_t t = tile_of(lo); t <= tl;) {
-            t = first_tile_geq(t, tl + 1, T);
-            if (t < 0) return -1;
-            const uint4 q = entry(t);
-            const int64_t ts = tile_start(t);
-            const int64_t a = max(lo, ts), b = min(hi, ts + kTile);
-            const uint32_t m = ie_max(q.x);
-            if (ie_all(q.x)) return a;                // every byte is m >= T
-            if (m == T) {
-                const uint32_t cnt = ie_cnt(q.x);
-                const int k_n = (int)min(cnt, (uint32_t)kIdxPos);
-                bool decided = false;
-                for (int k = 0; k < k_n; k++) {
-                    const int64_t p = ts + ie_pos(q, k);
-                    if (p >= b) { decided = true; break; }   // none in [a, b)
-                    if (p >= a) return p;
+        const int32_t ka = tile(lo), kb = tile(hi - 1);
+        for (int32_t k = ka; k <= kb;) {
+            need(k);
+            const int32_t last = min(kb, p0 + kWave - 1);
+            uint64_t cand = __ballot(ie_max(e.x) >= T) & lanes(k - p0, last - p0);
+            while (cand) {
+                const int32_t l = __builtin_ctzll(cand);
+                cand &= cand - 1;
+                const int32_t kt = p0 + l;
+                const uint32_t x = xword(l);
+                const int32_t ts = tstart(kt);
+                const int32_t a = max(lo, ts), b = min(hi, ts + kTile);
+                if (ie_all(x)) return a;               // every byte is m >= T
+                if (ie_max(x) == T) {                  // bytes >= T are those == m
+                    bool und;
+                    const uint32_t f = first_pos(l, x, (uint32_t)(a - ts),
+                                                 (uint32_t)(b - ts), und);
+                    if (f != kNoPos) return ts + (int32_t)f;
+                    if (!und) continue;
                 }
-                if (decided || cnt <= (uint32_t)kIdxPos) {
-                    t++;
-                    continue;
-                }
+                const int32_t j = bytes_first_geq(kt, a, b, T);
+                if (j >= 0) return j;
             }
-            const int64_t j = bytes_first_geq(t, a, b, T);
-            if (j >= 0) return j;
-            t++;
+            k = last + 1;
         }
         return -1;
     }

@@ -17,6 +17,10 @@ Recipes (the paper's datasets are not available; these stand in for them):
   each editing 1% of its 4 KiB regions by insert / delete / overwrite of 1-512
   random bytes (nightly backups, web and database snapshots).
 * ``lognormal_sizes(...)``: file sizes for many-file sets (source trees).
+* ``constant_blocks(n_blocks, seed)``: 64 KiB blocks each of one byte value,
+  the value changing from block to block (zero-filled and padded regions of
+  VM images and databases back to back; RAM chains never meet inside such
+  runs, the hardest case for the segment-parallel resolution).
 """
 import numpy as np
 
@@ -147,3 +151,11 @@ def many_files(sizes, seed):
     offs = np.zeros(sizes.size + 1, dtype=np.int64)
     np.cumsum(sizes, out=offs[1:])
     return uniform(int(offs[-1]), seed), offs
+
+
+def constant_blocks(n_blocks, seed, block=BLOCK):
+    """n_blocks blocks of ``block`` bytes, each a run of one uniformly drawn
+    byte value."""
+    rng = _rng(seed)
+    vals = rng.integers(0, 256, n_blocks, dtype=np.uint8)
+    return np.repeat(vals, block)

@@ -67,3 +67,12 @@ def test_edit_version():
     assert same.size > 0 and v.size != base.size or same.size > 0
     versions = list(datagen.snapshot_versions(4096 * 300, 3, 4))
     assert len(versions) == 4
+
+
+def test_constant_blocks():
+    x = datagen.constant_blocks(40, 3, block=1000)
+    assert x.size == 40000
+    b = x.reshape(40, 1000)
+    assert (b == b[:, :1]).all()
+    assert len(set(b[:, 0].tolist())) > 20
+    assert np.array_equal(x, datagen.constant_blocks(40, 3, block=1000))
