@@ -123,6 +123,20 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     int32_t s = start;
     bool stop = false;
     while (s < X.n && !stop) {
+        {
+            const int32_t L = s + M < X.n ? s + M : X.n;
+            int32_t c = -1;
+            if constexpr (RAM) {
+                if (s + w < L) c = X.ram_fast(s, w, L);
+            } else {
+                c = X.ae_fast(s, w, L);
+            }
+            if (c >= 0) {
+                if (emit(c)) break;
+                s = c;
+                continue;
+            }
+        }
         const int32_t re = X.const_run_end(s, w);
         if (re >= 0) {
             while (s + w <= re - 1) {

@@ -155,8 +155,10 @@ struct IdxWalker {
     int32_t ph;           // offset of base inside tile 0
     int32_t n;            // job length from base (clamped)
     int32_t ntiles;       // tiles from tile 0 to the job's end (clamped)
-    int32_t p0;           // first tile of the page (far below 0 before the first load)
+    int32_t p0;           // first tile of the page, a multiple of 32 (far below
+                          // 0 before the first load)
     uint4 e;              // this lane's summary (tile p0 + lane)
+    uint4 pf;             // the summary of tile p0 + 32 + lane, loaded ahead
     uint32_t reads_ebs, reads_rs;   // tiles whose bytes each pattern read
 
     __device__ void init(const JobView& J, const uint4* job_idx, int64_t base) {
@@ -173,12 +175,33 @@ struct IdxWalker {
     }
     __device__ __forceinline__ int32_t tile(int32_t pos) const { return (pos + ph) >> 10; }
     __device__ __forceinline__ int32_t tstart(int32_t k) const { return (k << 10) - ph; }
-    // make tile k part of the page (a page starts at the first tile needed)
+    // Pages start at multiples of 32 tiles.  Moving on by 32 takes the page
+    // loaded ahead (a walk moves forward, so its next page is usually there
+    // before it is needed); any other move loads the page where it lands.
+    // (lanes past the job's last tile load that tile and are cleared when
+    // the page is taken, so the load itself has no condition)
+    __device__ __forceinline__ uint4 page_load(int32_t q) const {
+        return idx[min(q + (int32_t)lane_id(), ntiles - 1)];
+    }
+    __device__ __forceinline__ void move_to(int32_t k) {
+        const int32_t q = k & ~31;
+        if (q != p0 + 32) pf = page_load(q);
+        e = q + (int32_t)lane_id() < ntiles ? pf : make_uint4(0, 0, 0, 0);
+        p0 = q;
+        // the copy above must precede the next load into pf: e is then never
+        // a load's destination, and its uses wait for no load in flight
+        __builtin_amdgcn_sched_barrier(0);
+        pf = page_load(q + 32);
+    }
+    // make tile k part of the page
     __device__ __forceinline__ void need(int32_t k) {
         if ((uint32_t)(k - p0) < (uint32_t)kWave) return;   // p0 starts far below
-        p0 = k;
-        const int32_t t = k + (int32_t)lane_id();
-        e = t < ntiles ? idx[t] : make_uint4(0, 0, 0, 0);
+        move_to(k);
+    }
+    // make tile k part of the page with at least 31 tiles after it
+    __device__ __forceinline__ void ahead(int32_t k) {
+        if ((uint32_t)(k - p0) < 32u) return;
+        move_to(k);
     }
 
     // ---- a tile's bytes (where the summary cannot decide)
@@ -269,6 +292,94 @@ struct IdxWalker {
                 return re - 1 >= s + w ? re : -1;
             }
         }
+    }
+
+    // ---- one chain step from the page's summaries alone
+    //
+    // Most steps need no byte and no second page: the tiles a window covers
+    // whole give its largest byte (unless an end tile holds a larger one),
+    // and the first byte at or above it is the first stored position of the
+    // first tile whose maximum equals it.  These return -1 whenever the
+    // summaries cannot decide; the exact patterns below then take the step.
+
+    // Largest byte of a range whose end tiles are page lanes la < lb - 1,
+    // from the tiles between them (m: this lane's tile maximum); -1 when an
+    // end tile holds a larger byte (its part in the range then decides).
+    __device__ __forceinline__ int32_t fast_max(int32_t la, int32_t lb, uint32_t m) const {
+        const int32_t l = (int32_t)lane_id();
+        const bool inner = l > la && l < lb;
+        if (__ballot(inner && m == 255u)) return 255;
+        const uint32_t T = uni(wave_max(inner ? m : 0u));
+        if (__ballot((l == la || l == lb) && m > T)) return -1;
+        return (int32_t)T;
+    }
+
+    // First position at or after `from` (in the tile of page lane lc) of a
+    // byte >= T (1 <= T): the position, kFar when no tile of the page from lc
+    // on holds one, or -1 when the summaries cannot decide.
+    static constexpr int32_t kFar = 0x7FFFFFFF;
+    __device__ __forceinline__ int32_t fast_first(int32_t lc, int32_t from, uint32_t T,
+                                                  uint32_t m) const {
+        uint64_t cand = __ballot(m >= T) & (~0ull << lc);
+        for (int i = 0; i < 2; i++) {              // a later tile always decides
+            if (!cand) return kFar;
+            const int32_t l = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint32_t x = xword(l);
+            const int32_t ts = tstart(p0 + l);
+            if (ie_all(x)) return max(from, ts);
+            if (ie_max(x) != T) return -1;         // bytes above T: not summarised
+            if (l != lc) return ts + (int32_t)(x >> 16);
+            bool und;
+            const uint32_t f = first_pos(l, x, (uint32_t)(from - ts), kTile, und);
+            if (f != kNoPos) return ts + (int32_t)f;
+            if (und) return -1;
+        }
+        return -1;
+    }
+
+    // RAM's next cut from chunk start s (s + w < L = min(s + M, n)), or -1.
+    __device__ __forceinline__ int32_t ram_fast(int32_t s, int32_t w, int32_t L) {
+        const int32_t ka = tile(s), kb = tile(s + w - 1), kc = tile(s + w);
+        ahead(ka);
+        const int32_t la = ka - p0, lb = kb - p0, lc = kc - p0;
+        if (lb - la < 2 || lc > kWave - 1) return -1;
+        const uint32_t m = ie_max(e.x);
+        if ((__ballot(ie_all(e.x)) >> la) & 1ull) return -1;   // a run of one value
+        const int32_t T = fast_max(la, lb, m);
+        if (T < 0) return -1;
+        if (T == 0) return s + w + 1;              // every byte is >= 0
+        const int32_t j = fast_first(lc, s + w, (uint32_t)T, m);
+        if (j == kFar) return tile(L - 1) - p0 < kWave ? L : -1;
+        if (j < 0) return -1;
+        return j < L ? j + 1 : L;
+    }
+
+    // AE's next cut from chunk start s (L = min(s + M, n)), or -1: the first
+    // occurrence p of the largest byte V of [s, s + w], final when nothing
+    // after the window up to p + w exceeds V.
+    __device__ __forceinline__ int32_t ae_fast(int32_t s, int32_t w, int32_t L) {
+        const int32_t hi = min(s + w + 1, L);
+        const int32_t ka = tile(s), kb = tile(hi - 1);
+        ahead(ka);
+        const int32_t la = ka - p0, lb = kb - p0;
+        if (lb - la < 2 || lb > kWave - 1) return -1;
+        const uint32_t m = ie_max(e.x);
+        if ((__ballot(ie_all(e.x)) >> la) & 1ull) return -1;   // a run of one value
+        const int32_t V = fast_max(la, lb, m);
+        if (V <= 0) return -1;
+        const int32_t p = fast_first(la, s, (uint32_t)V, m);
+        if (p < 0 || p >= hi) return -1;           // (kFar included)
+        if (V < 255) {
+            const int32_t nhi = min(p + w + 1, L);
+            if (nhi > hi) {
+                const int32_t ld = tile(hi) - p0, le = tile(nhi - 1) - p0;
+                if (le > kWave - 1) return -1;
+                const int32_t l = (int32_t)lane_id();
+                if (__ballot(l >= ld && l <= le && m > (uint32_t)V)) return -1;
+            }
+        }
+        return p + w < L ? p + w + 1 : L;
     }
 
     // ---- the two patterns, exact
