@@ -492,7 +492,9 @@ def serve_leg(pool, binding, datagen, torch, np):
     binding.serve(pool, reqs, total, budget_bytes=SERVE_BUDGET,
                   max_batch=SERVE_MAX_BATCH, slots=SERVE_SLOTS)
     del reqs
-    levels = [(l, SERVE_BUDGET) for l in SERVE_LOADS] + [(0.5, SERVE_SMALL_BUDGET)]
+    # the last level: a budget small enough that admission by memory binds
+    # (one batch in flight), at a load below what that budget sustains
+    levels = [(l, SERVE_BUDGET) for l in SERVE_LOADS] + [(0.1, SERVE_SMALL_BUDGET)]
     for i, (load, budget) in enumerate(levels):
         rate = load * peak / mean_size
         k = max(SERVE_MIN_REQUESTS, int(rate * SERVE_SECONDS))
@@ -521,7 +523,9 @@ def serve_leg(pool, binding, datagen, torch, np):
                "sustained_gbs": round(stats["bytes_done"] / stats["elapsed"] / 1e9, 2),
                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-               "failed": int((~ok).sum()), "launches": stats["launches"],
+               "failed": int((~ok).sum()),
+               "larger_than_budget": int((sizes + 8 * ((sizes - 1) // (wins + 1) + 1) > budget).sum()),
+               "launches": stats["launches"],
                "max_inflight": stats["max_inflight"],
                "max_queue": stats["max_queue"],
                "sample_identical_to_alone": bool(same)}
@@ -581,6 +585,23 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
+def profile_calls(args):
+    """The stream leg's single calls alone, without tuning or timing."""
+    import numpy as np
+    import torch
+    from paper_2508_05797_amd import binding, datagen
+    binding.lib()
+    binding.set_tuning()
+    x, _ = datagen.mixed_stream(STREAM_BLOCKS, STREAM_SEED)
+    d = torch.from_numpy(x).to("cuda:0")
+    for algo, w in ALGOS:
+        for _ in range(args.steps):
+            cuts = binding.chunk(d, algo, w, MAX_CHUNK)
+        torch.cuda.synchronize()
+        print(json.dumps({"algorithm": algo, "calls": args.steps,
+                          "cuts": int(cuts.numel())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,6 +610,10 @@ def main():
     ap.add_argument("--legs", default="stream,snap,batch,serve")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the oracle (no cpu_baseline, no checks)")
+    ap.add_argument("--profile-calls", action="store_true",
+                    help="only chunk the 1 GiB stream with single calls of "
+                         "each algorithm, --steps times (a short command for "
+                         "profilers; prints one line per algorithm)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy kernel three "
                          "times (reference for HBM byte counters)")
@@ -600,6 +625,9 @@ def main():
     legs = set(args.legs.split(","))
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.profile_calls:
+        profile_calls(args)
         return
 
     import numpy as np

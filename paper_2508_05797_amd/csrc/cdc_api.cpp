@@ -233,7 +233,7 @@ T* at(void* base, size_t off) {
 }
 
 struct Layout {
-    size_t err, idx, meta, spec, fix, rew, bmax, bpos, total;
+    size_t err, idx, succ, meta, spec, fix, rew, bmax, bpos, total;
 };
 
 // Tiles (1 KiB, address-aligned) of an n-byte buffer starting at data.
@@ -250,6 +250,7 @@ Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain,
     size_t off = 0;
     L.err = off;   off += 256;
     L.idx = off;   off = align_up(off + (chain ? tiles * 16 : 0), 256);
+    L.succ = off;  off = align_up(off + (chain ? tiles * 4 * kSuccSlots : 0), 256);
     L.meta = off;  off = align_up(off + items * sizeof(SegMeta), 256);
     L.spec = off;  off = align_up(off + slots * 4, 256);
     L.fix = off;   off = align_up(off + (chain ? slots * 4 : 0), 256);
@@ -263,6 +264,7 @@ Layout layout(uint64_t items, uint64_t slots, uint64_t blocks, bool chain,
 ChainWs chain_ws(void* base, const Layout& L) {
     ChainWs w;
     w.idx = at<uint4>(base, L.idx);
+    w.succ = at<uint32_t>(base, L.succ);
     w.meta = at<SegMeta>(base, L.meta);
     w.spec = at<uint32_t>(base, L.spec);
     w.fix = at<uint32_t>(base, L.fix);
@@ -310,7 +312,7 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
 }
 
 struct BatchLayout {
-    size_t err, nitems, bsum, jd, items, idx, meta, spec, fix, rew, bpos, bmax, total;
+    size_t err, nitems, bsum, jd, items, idx, succ, meta, spec, fix, rew, bpos, bmax, total;
 };
 
 BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
@@ -322,6 +324,7 @@ BatchLayout batch_layout(const BatchCaps& c, uint64_t n_jobs) {
     L.jd = off;     off = align_up(off + n_jobs * sizeof(JobDesc), 256);
     L.items = off;  off = align_up(off + c.items * sizeof(Item), 256);
     L.idx = off;    off = align_up(off + c.tiles * 16, 256);
+    L.succ = off;   off = align_up(off + c.tiles * 4 * kSuccSlots, 256);
     L.meta = off;   off = align_up(off + c.items * sizeof(SegMeta), 256);
     L.spec = off;   off = align_up(off + c.slots * 4, 256);
     L.fix = off;    off = align_up(off + c.slots * 4, 256);
@@ -673,6 +676,7 @@ int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
     ChainWs cw;
     cw.idx = at<uint4>(ws.dev, L.idx);
+    cw.succ = at<uint32_t>(ws.dev, L.succ);
     cw.meta = at<SegMeta>(ws.dev, L.meta);
     cw.spec = at<uint32_t>(ws.dev, L.spec);
     cw.fix = at<uint32_t>(ws.dev, L.fix);

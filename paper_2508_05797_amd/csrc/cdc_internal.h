@@ -102,12 +102,17 @@ struct Marks {
 // Workspace of the RAM / AE passes.
 struct ChainWs {
     uint4* idx;              // tile index entries (job's idx0 on)
+    uint32_t* succ;          // successor words, kSuccSlots per tile (same numbering)
     SegMeta* meta;           // per item
     uint32_t* spec;          // speculative cuts, cap per item (job slots)
     uint32_t* fix;           // fix-up cuts, cap per item
     uint32_t* rew;           // re-walk cuts, cap per item
     uint32_t* err;
 };
+
+// Successor words per tile: one per stored position of the tile's maximum
+// (seven) and one unused, so that a tile's words are two 16-byte loads.
+constexpr uint32_t kSuccSlots = 8;
 
 // Parallel resolution rounds after the fix-up before the ordered pass.
 constexpr int kRounds = 2;

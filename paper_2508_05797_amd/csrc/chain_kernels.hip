@@ -70,6 +70,174 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
     }
 }
 
+// ------------------------------------------------------------ successor pass
+
+// Each stored position of a tile's maximum is a possible chain node: for
+// RAM, the byte a cut lands after (it is at or above its window's maximum,
+// and a summary names it only as its tile's maximum); for AE, a final
+// target (the cut lands w + 1 bytes after it).  This pass works out, from
+// the summaries alone, where the chain goes from every node: the node of
+// the next cut, a forced cut (the chunk reaches max_chunk), the job's end,
+// or "unknown" where the summaries cannot decide.  A walker standing on a
+// node then takes the step as one lookup; on "unknown" it takes the step
+// itself.  Every answer recorded here is exact.
+constexpr int kSuccThreads = 256;                // four waves, 64 tiles each
+constexpr int kSuccSpan = 2 * kWave;             // tiles a wave sees: its 64 and 64 after
+constexpr int kSuccScan = 8;                     // tiles a range scan may cross
+
+// The summaries of tiles q .. q + 127 of one job, in LDS.
+struct SuccPages {
+    const uint4* pg;
+    int64_t q, shift, n;
+
+    __device__ bool has(int64_t k) const { return k - q < kSuccSpan; }
+    __device__ uint4 ent(int64_t k) const { return pg[k - q]; }
+    __device__ int64_t ts(int64_t k) const { return k * kTile - shift; }
+    __device__ int64_t tile(int64_t pos) const { return (pos + shift) >> 10; }
+
+    // first stored position >= a of a summary, with its slot (kNoPos if none)
+    __device__ static uint32_t first_stored(const uint4& E, uint32_t a, uint32_t& slot) {
+        const uint32_t ps[7] = {E.x >> 16, E.y & 0xFFFFu, E.y >> 16, E.z & 0xFFFFu,
+                                E.z >> 16, E.w & 0xFFFFu, E.w >> 16};
+        uint32_t f = kNoPos;
+        slot = 7;
+        for (int i = 6; i >= 0; i--)
+            if (ps[i] >= a) { f = ps[i]; slot = (uint32_t)i; }
+        return f;
+    }
+    // max(M, largest byte of [lo, hi) within tile k), or -1 if undecided
+    __device__ int32_t part_max(int64_t k, int64_t lo, int64_t hi, int32_t M) const {
+        const uint4 E = ent(k);
+        const int32_t m = (int32_t)ie_max(E.x);
+        if (m <= M) return M;
+        if (ie_all(E.x)) return m;
+        uint32_t sl;
+        const uint32_t a = (uint32_t)max(lo - ts(k), (int64_t)0);
+        const int64_t b = hi - ts(k);
+        const uint32_t f = first_stored(E, a, sl);
+        return f != kNoPos && (int64_t)f < b ? m : -1;
+    }
+    // largest byte of [lo, hi) (lo < hi), or -1 if undecided
+    __device__ int32_t range_max(int64_t lo, int64_t hi) const {
+        const int64_t ka = tile(lo), kb = tile(hi - 1);
+        if (!has(kb)) return -1;
+        if (ka == kb) return part_max(ka, lo, hi, -1);
+        int32_t I = 0;
+        for (int64_t k = ka + 1; k < kb && I < 255; k++) I = max(I, (int32_t)ie_max(ent(k).x));
+        if (I == 255) return 255;
+        I = part_max(ka, lo, hi, I);
+        if (I < 0) return -1;
+        return part_max(kb, lo, hi, I);
+    }
+    // first byte >= T (1..255) in [lo, hi): 1 and its tile, slot and offset
+    // when a summary names it, 0 when there is none, -1 if undecided
+    __device__ int first_geq(int64_t lo, int64_t hi, uint32_t T, int64_t& k_out,
+                             uint32_t& slot, uint32_t& off) const {
+        const int64_t k0 = tile(lo), k1 = tile(hi - 1);
+        for (int64_t k = k0; k <= k1; k++) {
+            // (a scan longer than a few tiles is left to the walker: a lane
+            // that scans holds up its whole wave)
+            if (!has(k) || k - k0 >= kSuccScan) return -1;
+            const uint4 E = ent(k);
+            const uint32_t m = ie_max(E.x);
+            if (m < T) continue;
+            if (m > T || ie_all(E.x)) return -1;
+            const uint32_t a = k == k0 ? (uint32_t)(lo - ts(k)) : 0u;
+            const uint32_t f = first_stored(E, a, slot);
+            if (f != kNoPos) {
+                if (ts(k) + (int64_t)f >= hi) return 0;
+                k_out = k;
+                off = f;
+                return 1;
+            }
+            if (ie_cnt(E.x) > (uint32_t)kIdxPos) return -1;
+        }
+        return 0;
+    }
+};
+
+// Successor word of the node at job position P in tile u (see kSuccUnknown).
+template <bool RAM>
+__device__ uint32_t succ_of(const SuccPages& G, int64_t u, int64_t P, int64_t w,
+                            int64_t M) {
+    const int64_t n = G.n;
+    int64_t k;
+    uint32_t slot, off;
+    if constexpr (RAM) {
+        const int64_t c = P + 1, L = min(c + M, n);
+        if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
+        const int32_t T = G.range_max(c, c + w);
+        if (T <= 0) return kSuccUnknown;
+        const int r = G.first_geq(c + w, L, (uint32_t)T, k, slot, off);
+        if (r < 0) return kSuccUnknown;
+        if (r == 0) return L == n ? kSuccEnd : kSuccForced;
+    } else {
+        const int64_t c = P + w + 1;
+        if (c >= n) return kSuccUnknown;
+        const int64_t L = min(c + M, n), hi = min(c + w + 1, L);
+        const int32_t V = G.range_max(c, hi);
+        if (V <= 0) return kSuccUnknown;
+        if (G.first_geq(c, hi, (uint32_t)V, k, slot, off) != 1) return kSuccUnknown;
+        const int64_t p = G.ts(k) + off;
+        const int64_t nhi = min(p + w + 1, L);
+        if (V < 255 && nhi > hi) {               // nothing greater may follow
+            const int64_t k1 = G.tile(nhi - 1);
+            if (!G.has(k1)) return kSuccUnknown;
+            for (int64_t j = G.tile(hi); j <= k1; j++)
+                if ((int32_t)ie_max(G.ent(j).x) > V) return kSuccUnknown;
+        }
+        if (p + w >= L) return L == n ? kSuccEnd : kSuccForced;
+    }
+    return (uint32_t)(k - u) << 23 | slot << 20 | off;
+}
+
+// Successor words of the tiles owned by one segment (as the index pass).
+template <bool RAM>
+__device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
+                          uint32_t* succ, uint4* pg) {
+    Source src;
+    src.init(J.data, (uint64_t)J.n);
+    const int64_t a = (int64_t)seg * J.seg;
+    const int64_t b = min(J.n, a + J.seg);
+    int64_t t0 = (a + src.shift + kTile - 1) >> 10;
+    if (seg == 0) t0 = 0;
+    const int64_t t1 = (b + src.shift + kTile - 1) >> 10;
+    const int64_t ntiles = (J.n + src.shift + kTile - 1) >> 10;
+    const uint4* jidx = idx + J.idx0;
+    uint32_t* jsucc = succ + J.idx0 * kSuccSlots;
+    const int64_t nw = blockDim.x / kWave, wv = uni(threadIdx.x / kWave);
+    const int l = (int)lane_id();
+    SuccPages G{pg, 0, src.shift, J.n};
+    for (int64_t q = t0 + wv * kWave; q < t1; q += nw * kWave) {
+        __builtin_amdgcn_wave_barrier();
+        for (int h = 0; h < kSuccSpan; h += kWave) {
+            const int64_t t = q + h + l;
+            pg[h + l] = t < ntiles ? jidx[t] : make_uint4(0, 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        G.q = q;
+        const int64_t u = q + l;
+        if (u < t1) {
+            const uint4 E = G.ent(u);
+            // (a tile of one value: a walker steps over it by itself, and no
+            // successor word names a position in it)
+            const uint32_t cnt = ie_all(E.x) ? 0u : min(ie_cnt(E.x), (uint32_t)kIdxPos);
+            const uint32_t ps[7] = {E.x >> 16, E.y & 0xFFFFu, E.y >> 16, E.z & 0xFFFFu,
+                                    E.z >> 16, E.w & 0xFFFFu, E.w >> 16};
+            uint32_t o[kSuccSlots];
+#pragma unroll
+            for (int i = 0; i < (int)kSuccSlots; i++) {
+                o[i] = kSuccUnknown;
+                if (i < kIdxPos && (uint32_t)i < cnt)
+                    o[i] = succ_of<RAM>(G, u, G.ts(u) + ps[i], J.w, J.M);
+            }
+            uint4* dst = (uint4*)(jsucc + u * kSuccSlots);
+            dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+            dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+        }
+    }
+}
+
 // ------------------------------------------------------------ next()
 
 // One chain step from chunk start s (offset from the walker's base): the
@@ -118,20 +286,45 @@ template <bool RAM, bool INV, class Emit>
 __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
                          int32_t start, Emit& emit) {
     IdxWalker<INV> X;
-    X.init(J, ws.idx + J.idx0, base);
+    X.init(J, ws.idx + J.idx0, ws.succ + J.idx0 * kSuccSlots, base);
     const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
+    // a cut lands 1 byte (RAM) or w + 1 bytes (AE) after its node
+    const int32_t delta = RAM ? 1 : w + 1;
     int32_t s = start;
+    int32_t nt = 0, ns = -1;           // the node of the cut at s (ns < 0: none)
     bool stop = false;
     while (s < X.n && !stop) {
+        if (ns >= 0) {                 // on a node: its successor word
+            X.ahead(nt);
+            const uint32_t sw = X.succ_word(nt - X.p0, (uint32_t)ns);
+            int32_t c;
+            if (sw < kSuccForced) {
+                nt += (int32_t)(sw >> 23);
+                ns = (int32_t)((sw >> 20) & 7u);
+                c = X.tstart(nt) + (int32_t)(sw & 1023u) + delta;
+            } else {
+                ns = -1;
+                c = sw == kSuccForced ? s + M : sw == kSuccEnd ? X.n : -1;
+            }
+            if (c > s && c <= X.n) {   // (always, for words of this pass)
+                if (emit(c)) break;
+                s = c;
+                continue;
+            }
+            ns = -1;
+        }
         {
             const int32_t L = s + M < X.n ? s + M : X.n;
             int32_t c = -1;
+            X.hit_s = -1;
             if constexpr (RAM) {
                 if (s + w < L) c = X.ram_fast(s, w, L);
             } else {
                 c = X.ae_fast(s, w, L);
             }
             if (c >= 0) {
+                nt = X.hit_t;
+                ns = X.hit_s;
                 if (emit(c)) break;
                 s = c;
                 continue;
@@ -436,6 +629,28 @@ __global__ __launch_bounds__(kIdxThreads) void k_index(Plan P, ChainWs ws,
     }
 }
 
+// Successor pass: one workgroup per item, as the index pass.
+template <bool RAM, bool ONE>
+__global__ __launch_bounds__(kSuccThreads) void k_succ(Plan P, ChainWs ws,
+                                                      uint32_t want) {
+    __shared__ uint4 pages[kSuccThreads / kWave][kSuccSpan];
+    uint4* my = pages[threadIdx.x / kWave];
+    if constexpr (ONE) {
+        const uint32_t wid = uni(blockIdx.x);
+        if (wid >= P.one_items) return;
+        const JobView J = view(P.one);
+        if (J.ok && J.algo == want) succ_item<RAM>(J, wid, ws.idx, ws.succ, my);
+    } else {
+        uint32_t first, last;
+        item_range(P, want, first, last);
+        for (uint32_t wid = first + uni(blockIdx.x); wid < last; wid += gridDim.x) {
+            const Item it = P.items[wid];
+            const JobView J = view(P.jobs[uni(it.job)]);
+            if (J.ok && J.algo == want) succ_item<RAM>(J, uni(it.seg), ws.idx, ws.succ, my);
+        }
+    }
+}
+
 template <bool RAM, bool INV, bool ONE>
 __global__ __launch_bounds__(kChainThreads) void k_spec(Plan P, ChainWs ws) {
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
@@ -654,6 +869,11 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
     if (part & kPartSpec) {
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
                    dim3(kIdxThreads), 0, st, P, ws, want);
+        const char* succ_name = RAM ? (ONE ? "successors_ram" : "successors_batch_ram")
+                                : INV ? (ONE ? "successors_ae_min" : "successors_batch_ae_min")
+                                      : (ONE ? "successors_ae" : "successors_batch_ae");
+        CDC_LAUNCH(mk, 1, succ_name, (k_succ<RAM, ONE>), dim3(items_upper),
+                   dim3(kSuccThreads), 0, st, P, ws, want);
         CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     }
     if (part & kPartFix)

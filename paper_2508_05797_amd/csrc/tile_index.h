@@ -32,6 +32,15 @@ namespace cdc {
 constexpr int kIdxPos = 7;                 // stored positions per tile
 constexpr uint32_t kNoPos = 0xFFFFu;
 
+// Successor words (one per stored position of a tile's maximum, written by
+// the successor pass): a node word dt << 23 | slot << 20 | offset names the
+// next node (dt tiles on, its slot among its tile's stored positions, its
+// offset in that tile); or the next cut is the forced one (chunk start +
+// max_chunk), or the job's end; or the summaries cannot decide.
+constexpr uint32_t kSuccForced = 1u << 30;
+constexpr uint32_t kSuccEnd = 2u << 30;
+constexpr uint32_t kSuccUnknown = 0xFFFFFFFFu;
+
 // entry dword 0: m | cnt << 8 (saturated at 127) | all_m << 15 | pos0 << 16;
 // dwords 1..3: pos1..pos6, 16 bits each (kNoPos: none); positions ascend.
 __device__ __forceinline__ uint32_t ie_max(uint32_t x) { return x & 0xFFu; }
@@ -150,6 +159,7 @@ __device__ __forceinline__ uint4 summarize_tile(uint4 v, int64_t tp, int64_t n,
 template <bool INV>
 struct IdxWalker {
     const uint4* idx;     // summary of tile k at idx[k]
+    const uint4* succ;    // successor words of tile k at succ[2k], succ[2k + 1]
     Source src;
     int64_t t0;           // the job's tile number of tile 0
     int32_t ph;           // offset of base inside tile 0
@@ -159,13 +169,19 @@ struct IdxWalker {
                           // 0 before the first load)
     uint4 e;              // this lane's summary (tile p0 + lane)
     uint4 pf;             // the summary of tile p0 + 32 + lane, loaded ahead
+    uint4 sa, sb;         // this lane's successor words (slots 0-3, 4-7)
+    uint4 psa, psb;       // those of tile p0 + 32 + lane, loaded ahead
+    int32_t hit_t, hit_s; // node of the last fast step's cut (tile, slot), or hit_s < 0
     uint32_t reads_ebs, reads_rs;   // tiles whose bytes each pattern read
 
-    __device__ void init(const JobView& J, const uint4* job_idx, int64_t base) {
+    __device__ void init(const JobView& J, const uint4* job_idx,
+                         const uint32_t* job_succ, int64_t base) {
         src.init(J.data, (uint64_t)J.n);
         t0 = (base + src.shift) >> 10;
         ph = (int32_t)((base + src.shift) & (kTile - 1));
         idx = job_idx + t0;
+        succ = (const uint4*)(job_succ + t0 * kSuccSlots);
+        hit_s = -1;
         const int64_t nrel = J.n - base;
         n = (int32_t)min(nrel, (int64_t)0x7FFFF000);
         const int64_t nt = (int64_t)((uint64_t)(J.n + src.shift + kTile - 1) >> 10) - t0;
@@ -180,18 +196,30 @@ struct IdxWalker {
     // before it is needed); any other move loads the page where it lands.
     // (lanes past the job's last tile load that tile and are cleared when
     // the page is taken, so the load itself has no condition)
-    __device__ __forceinline__ uint4 page_load(int32_t q) const {
-        return idx[min(q + (int32_t)lane_id(), ntiles - 1)];
+    __device__ __forceinline__ void page_load(int32_t q) {
+        const int32_t t = min(q + (int32_t)lane_id(), ntiles - 1);
+        pf = idx[t];
+        psa = succ[2 * t];
+        psb = succ[2 * t + 1];
     }
     __device__ __forceinline__ void move_to(int32_t k) {
         const int32_t q = k & ~31;
-        if (q != p0 + 32) pf = page_load(q);
-        e = q + (int32_t)lane_id() < ntiles ? pf : make_uint4(0, 0, 0, 0);
+        if (q != p0 + 32) page_load(q);
+        const bool in = q + (int32_t)lane_id() < ntiles;
+        e = in ? pf : make_uint4(0, 0, 0, 0);
+        sa = in ? psa : make_uint4(kSuccUnknown, kSuccUnknown, kSuccUnknown, kSuccUnknown);
+        sb = in ? psb : make_uint4(kSuccUnknown, kSuccUnknown, kSuccUnknown, kSuccUnknown);
         p0 = q;
-        // the copy above must precede the next load into pf: e is then never
-        // a load's destination, and its uses wait for no load in flight
+        // the copies above must precede the next loads: e, sa and sb are then
+        // never a load's destination, and their uses wait for no load in flight
         __builtin_amdgcn_sched_barrier(0);
-        pf = page_load(q + 32);
+        page_load(q + 32);
+    }
+    // successor word of slot `slot` of page lane l
+    __device__ __forceinline__ uint32_t succ_word(int32_t l, uint32_t slot) const {
+        const uint4 h = slot < 4 ? sa : sb;
+        const uint32_t v = (slot & 2) ? ((slot & 1) ? h.w : h.z) : ((slot & 1) ? h.y : h.x);
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
     }
     // make tile k part of the page
     __device__ __forceinline__ void need(int32_t k) {
@@ -316,26 +344,41 @@ struct IdxWalker {
 
     // First position at or after `from` (in the tile of page lane lc) of a
     // byte >= T (1 <= T): the position, kFar when no tile of the page from lc
-    // on holds one, or -1 when the summaries cannot decide.
+    // on holds one, or -1 when the summaries cannot decide.  Every lane
+    // works out its own tile's answer, so the step costs two ballots and one
+    // lane read, not a branch per tile.
     static constexpr int32_t kFar = 0x7FFFFFFF;
     __device__ __forceinline__ int32_t fast_first(int32_t lc, int32_t from, uint32_t T,
-                                                  uint32_t m) const {
-        uint64_t cand = __ballot(m >= T) & (~0ull << lc);
-        for (int i = 0; i < 2; i++) {              // a later tile always decides
-            if (!cand) return kFar;
-            const int32_t l = __builtin_ctzll(cand);
-            cand &= cand - 1;
-            const uint32_t x = xword(l);
-            const int32_t ts = tstart(p0 + l);
-            if (ie_all(x)) return max(from, ts);
-            if (ie_max(x) != T) return -1;         // bytes above T: not summarised
-            if (l != lc) return ts + (int32_t)(x >> 16);
-            bool und;
-            const uint32_t f = first_pos(l, x, (uint32_t)(from - ts), kTile, und);
-            if (f != kNoPos) return ts + (int32_t)f;
-            if (und) return -1;
+                                                  uint32_t m) {
+        const int32_t l = (int32_t)lane_id();
+        const uint32_t a = l == lc ? (uint32_t)(from - tstart(p0 + lc)) : 0u;
+        // the first stored position >= a (positions ascend; unused slots
+        // hold kNoPos, which is above every offset, so no count is needed)
+        const uint32_t ps[7] = {e.x >> 16, e.y & 0xFFFFu, e.y >> 16, e.z & 0xFFFFu,
+                                e.z >> 16, e.w & 0xFFFFu, e.w >> 16};
+        uint32_t f = kNoPos, fi = 7;
+#pragma unroll
+        for (int i = 6; i >= 0; i--) {
+            fi = ps[i] >= a ? (uint32_t)i : fi;
+            f = ps[i] >= a ? ps[i] : f;
         }
-        return -1;
+        const bool all = ie_all(e.x);
+        const bool ge = l >= lc && m >= T;
+        // a byte >= T located: the tile is one value, or its maximum is T
+        // (every byte >= T equals it) and a stored position qualifies
+        const bool hit = ge && (all || (m == T && f != kNoPos));
+        // a byte >= T may lie where no stored position says
+        const bool lost = ge && !hit && (m != T || ie_cnt(e.x) > (uint32_t)kIdxPos);
+        const uint64_t H = __ballot(hit), X = __ballot(lost);
+        if (!H) return X ? -1 : kFar;
+        const int32_t lh = __builtin_ctzll(H);
+        if (X & ((2ull << lh) - 1ull)) return -1;   // (a lost tile at or before)
+        const uint32_t pos = all ? a : f;
+        // the node: a stored position (a tile of one value gives none)
+        hit_t = p0 + lh;
+        hit_s = (int32_t)__builtin_amdgcn_readlane((int)(all ? 7u : fi), lh);
+        if (hit_s == 7) hit_s = -1;
+        return tstart(p0 + lh) + __builtin_amdgcn_readlane((int)pos, lh);
     }
 
     // RAM's next cut from chunk start s (s + w < L = min(s + M, n)), or -1.
@@ -352,7 +395,9 @@ struct IdxWalker {
         const int32_t j = fast_first(lc, s + w, (uint32_t)T, m);
         if (j == kFar) return tile(L - 1) - p0 < kWave ? L : -1;
         if (j < 0) return -1;
-        return j < L ? j + 1 : L;
+        if (j < L) return j + 1;
+        hit_s = -1;                                // a forced cut: no node
+        return L;
     }
 
     // AE's next cut from chunk start s (L = min(s + M, n)), or -1: the first
@@ -379,7 +424,9 @@ struct IdxWalker {
                 if (__ballot(l >= ld && l <= le && m > (uint32_t)V)) return -1;
             }
         }
-        return p + w < L ? p + w + 1 : L;
+        if (p + w < L) return p + w + 1;
+        hit_s = -1;                                // a forced cut: no node
+        return L;
     }
 
     // ---- the two patterns, exact

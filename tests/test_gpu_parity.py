@@ -159,6 +159,33 @@ def test_resolution_rounds(algo, seg):
         binding.set_tuning(0, 0)
 
 
+def dense_max(n, rate, rng, hi=255, lo_cap=255):
+    """Bytes below lo_cap with the value hi planted at the given rate: how
+    many of a tile's maxima there are (and whether its summary lists them
+    all) is set by the rate."""
+    x = rng.integers(0, lo_cap, n, dtype=np.uint8)
+    x[rng.random(n) < rate] = hi
+    return x
+
+
+@pytest.mark.parametrize("algo", ["ram", "ae", "ae_min"])
+@pytest.mark.parametrize("w,M", [(1024, 65536), (3000, 3001), (4096, 8192),
+                                 (4096, 65536), (5000, 131072), (2047, 60000)])
+def test_tile_maxima_density(algo, w, M):
+    # chains stepping from one summarised maximum to the next: tiles with
+    # one, a few, exactly seven and many maxima; maxima spaced near the
+    # window; text whose largest symbol is rare or common
+    rng = np.random.default_rng(w * 7 + M)
+    n = (3 << 20) + 777
+    for rate in (1 / 20000, 1 / 4096, 1 / 1024, 1 / 146, 1 / 64, 1 / 8):
+        check(dense_max(n, rate, rng), algo, w, M, tag="dense%g" % rate)
+    check(dense_max(n, 1 / 300, rng, hi=122, lo_cap=122), algo, w, M, tag="text_hi")
+    spaced = rng.integers(0, 200, n, dtype=np.uint8)
+    spaced[::w + 1] = 255
+    spaced[w // 2::3 * w] = 255
+    check(spaced, algo, w, M, tag="spaced")
+
+
 @pytest.mark.parametrize("w,M", [(1500, 9000), (4096, 65536), (1500, 1501),
                                  (4096, 4097)])
 def test_constant_segments(w, M):
