@@ -85,15 +85,18 @@ constexpr int kSuccThreads = 256;                // four waves, 64 tiles each
 constexpr int kSuccSpan = 2 * kWave;             // tiles a wave sees: its 64 and 64 after
 constexpr int kSuccScan = 8;                     // tiles a range scan may cross
 
-// The summaries of tiles q .. q + 127 of one job, in LDS.
+// The summaries of tiles q .. q + 127 of one job, in LDS.  Positions are
+// 32-bit offsets from the first byte of tile q (tile j of the page starts
+// at 1024 j), and n is the job's end in the same terms (clamped far out).
 struct SuccPages {
     const uint4* pg;
-    int64_t q, shift, n;
+    int32_t n;
 
-    __device__ bool has(int64_t k) const { return k - q < kSuccSpan; }
-    __device__ uint4 ent(int64_t k) const { return pg[k - q]; }
-    __device__ int64_t ts(int64_t k) const { return k * kTile - shift; }
-    __device__ int64_t tile(int64_t pos) const { return (pos + shift) >> 10; }
+    __device__ static bool has(int32_t k) { return k < kSuccSpan; }
+    __device__ uint4 ent(int32_t k) const { return pg[k]; }
+    __device__ uint32_t word0(int32_t k) const { return pg[k].x; }
+    __device__ static int32_t ts(int32_t k) { return k << 10; }
+    __device__ static int32_t tile(int32_t pos) { return pos >> 10; }
 
     // first stored position >= a of a summary, with its slot (kNoPos if none)
     __device__ static uint32_t first_stored(const uint4& E, uint32_t a, uint32_t& slot) {
@@ -101,29 +104,30 @@ struct SuccPages {
                                 E.z >> 16, E.w & 0xFFFFu, E.w >> 16};
         uint32_t f = kNoPos;
         slot = 7;
-        for (int i = 6; i >= 0; i--)
-            if (ps[i] >= a) { f = ps[i]; slot = (uint32_t)i; }
+#pragma unroll
+        for (int i = 6; i >= 0; i--) {
+            slot = ps[i] >= a ? (uint32_t)i : slot;
+            f = ps[i] >= a ? ps[i] : f;
+        }
         return f;
     }
     // max(M, largest byte of [lo, hi) within tile k), or -1 if undecided
-    __device__ int32_t part_max(int64_t k, int64_t lo, int64_t hi, int32_t M) const {
-        const uint4 E = ent(k);
-        const int32_t m = (int32_t)ie_max(E.x);
+    __device__ int32_t part_max(int32_t k, int32_t lo, int32_t hi, int32_t M) const {
+        const uint32_t x = word0(k);
+        const int32_t m = (int32_t)ie_max(x);
         if (m <= M) return M;
-        if (ie_all(E.x)) return m;
+        if (ie_all(x)) return m;
         uint32_t sl;
-        const uint32_t a = (uint32_t)max(lo - ts(k), (int64_t)0);
-        const int64_t b = hi - ts(k);
-        const uint32_t f = first_stored(E, a, sl);
-        return f != kNoPos && (int64_t)f < b ? m : -1;
+        const uint32_t f = first_stored(ent(k), (uint32_t)max(lo - ts(k), 0), sl);
+        return f != kNoPos && (int32_t)f < hi - ts(k) ? m : -1;
     }
     // largest byte of [lo, hi) (lo < hi), or -1 if undecided
-    __device__ int32_t range_max(int64_t lo, int64_t hi) const {
-        const int64_t ka = tile(lo), kb = tile(hi - 1);
+    __device__ int32_t range_max(int32_t lo, int32_t hi) const {
+        const int32_t ka = tile(lo), kb = tile(hi - 1);
         if (!has(kb)) return -1;
         if (ka == kb) return part_max(ka, lo, hi, -1);
         int32_t I = 0;
-        for (int64_t k = ka + 1; k < kb && I < 255; k++) I = max(I, (int32_t)ie_max(ent(k).x));
+        for (int32_t k = ka + 1; k < kb && I < 255; k++) I = max(I, (int32_t)ie_max(word0(k)));
         if (I == 255) return 255;
         I = part_max(ka, lo, hi, I);
         if (I < 0) return -1;
@@ -131,40 +135,39 @@ struct SuccPages {
     }
     // first byte >= T (1..255) in [lo, hi): 1 and its tile, slot and offset
     // when a summary names it, 0 when there is none, -1 if undecided
-    __device__ int first_geq(int64_t lo, int64_t hi, uint32_t T, int64_t& k_out,
+    __device__ int first_geq(int32_t lo, int32_t hi, uint32_t T, int32_t& k_out,
                              uint32_t& slot, uint32_t& off) const {
-        const int64_t k0 = tile(lo), k1 = tile(hi - 1);
-        for (int64_t k = k0; k <= k1; k++) {
+        const int32_t k0 = tile(lo), k1 = tile(hi - 1);
+        for (int32_t k = k0; k <= k1; k++) {
             // (a scan longer than a few tiles is left to the walker: a lane
             // that scans holds up its whole wave)
             if (!has(k) || k - k0 >= kSuccScan) return -1;
-            const uint4 E = ent(k);
-            const uint32_t m = ie_max(E.x);
+            const uint32_t x = word0(k);
+            const uint32_t m = ie_max(x);
             if (m < T) continue;
-            if (m > T || ie_all(E.x)) return -1;
-            const uint32_t a = k == k0 ? (uint32_t)(lo - ts(k)) : 0u;
-            const uint32_t f = first_stored(E, a, slot);
+            if (m > T || ie_all(x)) return -1;
+            const uint32_t f = first_stored(ent(k), k == k0 ? (uint32_t)(lo - ts(k)) : 0u, slot);
             if (f != kNoPos) {
-                if (ts(k) + (int64_t)f >= hi) return 0;
+                if (ts(k) + (int32_t)f >= hi) return 0;
                 k_out = k;
                 off = f;
                 return 1;
             }
-            if (ie_cnt(E.x) > (uint32_t)kIdxPos) return -1;
+            if (ie_cnt(x) > (uint32_t)kIdxPos) return -1;
         }
         return 0;
     }
 };
 
-// Successor word of the node at job position P in tile u (see kSuccUnknown).
+// Successor word of the node at page position P in page tile u.
 template <bool RAM>
-__device__ uint32_t succ_of(const SuccPages& G, int64_t u, int64_t P, int64_t w,
-                            int64_t M) {
-    const int64_t n = G.n;
-    int64_t k;
+__device__ uint32_t succ_of(const SuccPages& G, int32_t u, int32_t P, int32_t w,
+                            int32_t M) {
+    const int32_t n = G.n;
+    int32_t k;
     uint32_t slot, off;
     if constexpr (RAM) {
-        const int64_t c = P + 1, L = min(c + M, n);
+        const int32_t c = P + 1, L = min(c + M, n);
         if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
         const int32_t T = G.range_max(c, c + w);
         if (T <= 0) return kSuccUnknown;
@@ -172,19 +175,19 @@ __device__ uint32_t succ_of(const SuccPages& G, int64_t u, int64_t P, int64_t w,
         if (r < 0) return kSuccUnknown;
         if (r == 0) return L == n ? kSuccEnd : kSuccForced;
     } else {
-        const int64_t c = P + w + 1;
+        const int32_t c = P + w + 1;
         if (c >= n) return kSuccUnknown;
-        const int64_t L = min(c + M, n), hi = min(c + w + 1, L);
+        const int32_t L = min(c + M, n), hi = min(c + w + 1, L);
         const int32_t V = G.range_max(c, hi);
         if (V <= 0) return kSuccUnknown;
         if (G.first_geq(c, hi, (uint32_t)V, k, slot, off) != 1) return kSuccUnknown;
-        const int64_t p = G.ts(k) + off;
-        const int64_t nhi = min(p + w + 1, L);
+        const int32_t p = G.ts(k) + (int32_t)off;
+        const int32_t nhi = min(p + w + 1, L);
         if (V < 255 && nhi > hi) {               // nothing greater may follow
-            const int64_t k1 = G.tile(nhi - 1);
+            const int32_t k1 = G.tile(nhi - 1);
             if (!G.has(k1)) return kSuccUnknown;
-            for (int64_t j = G.tile(hi); j <= k1; j++)
-                if ((int32_t)ie_max(G.ent(j).x) > V) return kSuccUnknown;
+            for (int32_t j = G.tile(hi); j <= k1; j++)
+                if ((int32_t)ie_max(G.word0(j)) > V) return kSuccUnknown;
         }
         if (p + w >= L) return L == n ? kSuccEnd : kSuccForced;
     }
@@ -207,7 +210,9 @@ __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
     uint32_t* jsucc = succ + J.idx0 * kSuccSlots;
     const int64_t nw = blockDim.x / kWave, wv = uni(threadIdx.x / kWave);
     const int l = (int)lane_id();
-    SuccPages G{pg, 0, src.shift, J.n};
+    // (windows and chunks are below 2^28 bytes, so 32-bit page offsets hold
+    // every position a node's step reaches)
+    const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
     for (int64_t q = t0 + wv * kWave; q < t1; q += nw * kWave) {
         __builtin_amdgcn_wave_barrier();
         for (int h = 0; h < kSuccSpan; h += kWave) {
@@ -215,23 +220,25 @@ __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
             pg[h + l] = t < ntiles ? jidx[t] : make_uint4(0, 0, 0, 0);
         }
         __builtin_amdgcn_wave_barrier();
-        G.q = q;
-        const int64_t u = q + l;
-        if (u < t1) {
-            const uint4 E = G.ent(u);
+        const int64_t base = q * kTile - src.shift;          // page offset 0
+        SuccPages G{pg, (int32_t)min(J.n - base, (int64_t)0x3FFFFFFF)};
+        if (q + l < t1) {
+            const uint4 E = G.ent(l);
             // (a tile of one value: a walker steps over it by itself, and no
             // successor word names a position in it)
             const uint32_t cnt = ie_all(E.x) ? 0u : min(ie_cnt(E.x), (uint32_t)kIdxPos);
-            const uint32_t ps[7] = {E.x >> 16, E.y & 0xFFFFu, E.y >> 16, E.z & 0xFFFFu,
-                                    E.z >> 16, E.w & 0xFFFFu, E.w >> 16};
             uint32_t o[kSuccSlots];
 #pragma unroll
-            for (int i = 0; i < (int)kSuccSlots; i++) {
-                o[i] = kSuccUnknown;
-                if (i < kIdxPos && (uint32_t)i < cnt)
-                    o[i] = succ_of<RAM>(G, u, G.ts(u) + ps[i], J.w, J.M);
+            for (int i = 0; i < (int)kSuccSlots; i++) o[i] = kSuccUnknown;
+            for (uint32_t i = 0; i < (uint32_t)kIdxPos; i++) {
+                if (i >= cnt) break;
+                const uint32_t word = i == 0 ? E.x : i <= 2 ? E.y : i <= 4 ? E.z : E.w;
+                const uint32_t pos = i == 0 ? word >> 16 : (i & 1) ? word & 0xFFFFu : word >> 16;
+                const uint32_t r = succ_of<RAM>(G, l, SuccPages::ts(l) + (int32_t)pos, w, M);
+#pragma unroll
+                for (int j = 0; j < kIdxPos; j++) o[j] = (uint32_t)j == i ? r : o[j];
             }
-            uint4* dst = (uint4*)(jsucc + u * kSuccSlots);
+            uint4* dst = (uint4*)(jsucc + (q + l) * kSuccSlots);
             dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
             dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
         }
