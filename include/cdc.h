@@ -100,15 +100,17 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
  * cdc_chunk for callers that cannot allocate device memory: code under HIP
  * graph capture that has no reservation, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments, semantics and results as
- * cdc_chunk, but the library's working memory is a fixed 32 MiB array per
+ * cdc_chunk, but the library's working memory is a fixed 64 MiB array per
  * device inside the library (held from load until the process ends)
  * instead of a per-stream workspace: nothing is allocated, no workspace is
  * created, and no event is recorded (profiling does not apply).
- * Limit: the call's workspace (per segment of the chain search a record and
- * three cut lists of about (segment + max_chunk) / (window + 1) slots; for
- * MAXP, block summaries of the input and a candidate list) must fit the
- * 32 MiB; with the built-in tuning that covers, for example, about 8 GiB
- * for RAM or AE at window 4096 and about 2.5 GiB for MAXP at window 2048.
+ * Limit: the call's workspace (for RAM / AE, 48 bytes of tile summaries and
+ * successor words per KiB of input, and per segment of the chain search a
+ * record and three cut lists of about (segment + max_chunk) / (window + 1)
+ * slots; for MAXP, block summaries of the input and a candidate list) must
+ * fit the 64 MiB; with the built-in tuning that covers, for example, about
+ * 1.2 GiB for RAM or AE at window 4096 and about 5.5 GiB for MAXP at
+ * window 2048.
  * Larger requests are refused with CDC_ENOMEM before anything is enqueued,
  * cdc_last_error() stating the bytes needed.  All calls on one device share
  * the array: calls that can overlap on the device (on different streams,
@@ -294,6 +296,25 @@ int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
  * indicates a library bug; 0 when nothing was flagged), or CDC_EHIP.
  */
 int cdc_check_device_errors(hipStream_t stream);
+
+/*
+ * How the last cdc_chunk call on `stream` (RAM, AE or AE-Min) decided its
+ * chunks: the speculation pass walks every segment once, and each of its
+ * chunks was decided by a successor word, by the fast step from the tile
+ * summaries, as a chunk of w + 1 inside a run of one byte value, or by the
+ * exact patterns (Section 4.1's extreme byte search and Section 4.2's range
+ * scan, reading a tile's bytes where its summary cannot decide).
+ * tiles_read_* count the tiles whose bytes each pattern read in all passes
+ * of the call (saturated at 65,535 per segment and pass).  A diagnostic:
+ * synchronises `stream`; all counts are 0 when the last call was MAXP, a
+ * batch, or absent.  Returns CDC_OK, CDC_EINVAL (out is null) or CDC_EHIP.
+ */
+typedef struct {
+    uint64_t segments;
+    uint64_t steps_successor, steps_fast, steps_run, steps_exact;
+    uint64_t tiles_read_ebs, tiles_read_rs;
+} cdc_walk_stats_t;
+int cdc_walk_stats(hipStream_t stream, cdc_walk_stats_t* out);
 
 #ifdef __cplusplus
 }

@@ -92,6 +92,8 @@ def lib():
                                        ctypes.POINTER(ctypes.c_double), _I]
         L.cdc_check_device_errors.restype = _I
         L.cdc_check_device_errors.argtypes = [_V]
+        L.cdc_walk_stats.restype = _I
+        L.cdc_walk_stats.argtypes = [_V, _V]
         L.cdc_stream_open.restype = _I
         L.cdc_stream_open.argtypes = [_I, ctypes.POINTER(Params), _SZ, _V,
                                       ctypes.POINTER(ctypes.c_void_p)]
@@ -223,6 +225,17 @@ def kernel_times(stream=None, max_kernels=16):
     if k < 0:
         _check(k)
     return {names[i].decode(): (int(calls[i]), float(tot[i])) for i in range(k)}
+
+
+def walk_stats(stream=None):
+    """How the last single RAM / AE call on the stream decided its chunks
+    (synchronises the stream): segments, speculation steps by kind, tiles
+    whose bytes each pattern read."""
+    out = (ctypes.c_uint64 * 7)()
+    _check(lib().cdc_walk_stats(_stream(stream), out))
+    keys = ("segments", "steps_successor", "steps_fast", "steps_run",
+            "steps_exact", "tiles_read_ebs", "tiles_read_rs")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 def reserve(max_total_bytes, max_jobs, min_window, max_chunk, stream=None):

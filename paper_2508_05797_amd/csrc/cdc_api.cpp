@@ -136,6 +136,9 @@ struct Workspace {
     // allocated until cdc_release (or until the stream's workspace is
     // dropped); growth is geometric, which bounds what they add up to.
     std::vector<void*> retired;
+    // the last single RAM / AE call on the stream (for cdc_walk_stats)
+    size_t last_meta = 0;
+    uint32_t last_items = 0;
     // reservation for batches
     uint32_t res_jobs = 0;
     BatchCaps res_caps{};
@@ -426,7 +429,7 @@ int enqueue_one(const JobDesc& jd, const Layout& L, void* base, int wpb,
 // hipGetSymbolAddress, once per device, with that device current, and only
 // that address is ever passed to kernels.  Its first word collects the
 // kernels' sticky error flags (cleared by cdc_check_device_errors).
-constexpr size_t kScratchBytes = 32u << 20;
+constexpr size_t kScratchBytes = 64u << 20;
 static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 constexpr int kMaxDevices = 64;
 void* g_scratch_ptr[kMaxDevices] = {};
@@ -536,6 +539,8 @@ int cdc_chunk(cdc_algo algo, const cdc_params* p, const uint8_t* data,
     if (rc != CDC_OK) return rc;
     ws.marks.level = g_profile_level;
     Marks* mk = g_profile_level > 0 ? &ws.marks : nullptr;
+    ws.last_items = jd.algo == kMaxp ? 0u : jd.nseg;
+    ws.last_meta = L.meta;
     return enqueue_one(jd, L, ws.dev, wpb, stream, mk);
 }
 
@@ -782,6 +787,30 @@ int cdc_kernel_times(hipStream_t stream, const char** names, uint32_t* calls,
     }
     ws.marks.recs.clear();
     return used;
+}
+
+int cdc_walk_stats(hipStream_t stream, cdc_walk_stats_t* out) {
+    if (out == nullptr) return CDC_EINVAL;
+    std::lock_guard<std::mutex> g(g_mu);
+    Workspace& ws = workspace_for(stream);
+    *out = cdc_walk_stats_t{};
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) { set_error("hipStreamSynchronize", e); return CDC_EHIP; }
+    if (ws.last_items == 0 || ws.dev == nullptr) return CDC_OK;
+    std::vector<SegMeta> m(ws.last_items);
+    e = hipMemcpy(m.data(), static_cast<char*>(ws.dev) + ws.last_meta,
+                  m.size() * sizeof(SegMeta), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { set_error("hipMemcpy", e); return CDC_EHIP; }
+    out->segments = m.size();
+    for (const SegMeta& r : m) {
+        out->steps_successor += r.steps[0];
+        out->steps_fast += r.steps[1];
+        out->steps_run += r.steps[2];
+        out->steps_exact += r.steps[3];
+        out->tiles_read_ebs += r.reads & 0xFFFFu;
+        out->tiles_read_rs += r.reads >> 16;
+    }
+    return CDC_OK;
 }
 
 int cdc_check_device_errors(hipStream_t stream) {

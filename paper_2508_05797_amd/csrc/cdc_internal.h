@@ -63,6 +63,10 @@ struct SegMeta {
     uint32_t count;          // cuts of the current resolution
     uint32_t npieces;
     uint32_t reads;          // tiles whose bytes the walkers of this item read
+                             // (extreme byte search: low half; range scan: high half)
+    uint32_t steps[4];       // the speculation walk's chunks by how each was
+                             // decided: successor word, fast step, run of one
+                             // value, exact patterns
     uint32_t claim;          // settling pass that holds this segment
     Piece pieces[3];
 };

@@ -72,15 +72,17 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
 
 // ------------------------------------------------------------ successor pass
 
-// Each stored position of a tile's maximum is a possible chain node: for
-// RAM, the byte a cut lands after (it is at or above its window's maximum,
-// and a summary names it only as its tile's maximum); for AE, a final
-// target (the cut lands w + 1 bytes after it).  This pass works out, from
-// the summaries alone, where the chain goes from every node: the node of
-// the next cut, a forced cut (the chunk reaches max_chunk), the job's end,
-// or "unknown" where the summaries cannot decide.  A walker standing on a
-// node then takes the step as one lookup; on "unknown" it takes the step
-// itself.  Every answer recorded here is exact.
+// Each stored position P of a tile's maximum is a possible RAM chain node:
+// a cut lands right after a byte at or above its window's maximum, and
+// where the summaries decide a step that byte is its tile's maximum.  This
+// pass works out, from the summaries alone, where the chain goes from every
+// node: the node of the next cut, a forced cut (the chunk reaches
+// max_chunk), the job's end, or "unknown" where the summaries cannot decide.
+// A walker standing on a node then takes the step as one lookup; on
+// "unknown" it takes the step itself.  Every answer recorded here is exact.
+// (AE chains meet within a few chunks of each other, so their walks are
+// short and the same table for AE cost about what it saved; AE walks
+// without it.)
 constexpr int kSuccThreads = 256;                // four waves, 64 tiles each
 constexpr int kSuccSpan = 2 * kWave;             // tiles a wave sees: its 64 and 64 after
 constexpr int kSuccScan = 8;                     // tiles a range scan may cross
@@ -159,43 +161,24 @@ struct SuccPages {
     }
 };
 
-// Successor word of the node at page position P in page tile u.
-template <bool RAM>
+// Successor word of the RAM node at page position P in page tile u: the
+// chunk that starts right after P.
 __device__ uint32_t succ_of(const SuccPages& G, int32_t u, int32_t P, int32_t w,
                             int32_t M) {
     const int32_t n = G.n;
     int32_t k;
     uint32_t slot, off;
-    if constexpr (RAM) {
-        const int32_t c = P + 1, L = min(c + M, n);
-        if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
-        const int32_t T = G.range_max(c, c + w);
-        if (T <= 0) return kSuccUnknown;
-        const int r = G.first_geq(c + w, L, (uint32_t)T, k, slot, off);
-        if (r < 0) return kSuccUnknown;
-        if (r == 0) return L == n ? kSuccEnd : kSuccForced;
-    } else {
-        const int32_t c = P + w + 1;
-        if (c >= n) return kSuccUnknown;
-        const int32_t L = min(c + M, n), hi = min(c + w + 1, L);
-        const int32_t V = G.range_max(c, hi);
-        if (V <= 0) return kSuccUnknown;
-        if (G.first_geq(c, hi, (uint32_t)V, k, slot, off) != 1) return kSuccUnknown;
-        const int32_t p = G.ts(k) + (int32_t)off;
-        const int32_t nhi = min(p + w + 1, L);
-        if (V < 255 && nhi > hi) {               // nothing greater may follow
-            const int32_t k1 = G.tile(nhi - 1);
-            if (!G.has(k1)) return kSuccUnknown;
-            for (int32_t j = G.tile(hi); j <= k1; j++)
-                if ((int32_t)ie_max(G.word0(j)) > V) return kSuccUnknown;
-        }
-        if (p + w >= L) return L == n ? kSuccEnd : kSuccForced;
-    }
+    const int32_t c = P + 1, L = min(c + M, n);
+    if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
+    const int32_t T = G.range_max(c, c + w);
+    if (T <= 0) return kSuccUnknown;
+    const int r = G.first_geq(c + w, L, (uint32_t)T, k, slot, off);
+    if (r < 0) return kSuccUnknown;
+    if (r == 0) return L == n ? kSuccEnd : kSuccForced;
     return (uint32_t)(k - u) << 23 | slot << 20 | off;
 }
 
 // Successor words of the tiles owned by one segment (as the index pass).
-template <bool RAM>
 __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
                           uint32_t* succ, uint4* pg) {
     Source src;
@@ -234,7 +217,7 @@ __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
                 if (i >= cnt) break;
                 const uint32_t word = i == 0 ? E.x : i <= 2 ? E.y : i <= 4 ? E.z : E.w;
                 const uint32_t pos = i == 0 ? word >> 16 : (i & 1) ? word & 0xFFFFu : word >> 16;
-                const uint32_t r = succ_of<RAM>(G, l, SuccPages::ts(l) + (int32_t)pos, w, M);
+                const uint32_t r = succ_of(G, l, SuccPages::ts(l) + (int32_t)pos, w, M);
 #pragma unroll
                 for (int j = 0; j < kIdxPos; j++) o[j] = (uint32_t)j == i ? r : o[j];
             }
@@ -291,9 +274,15 @@ __device__ __forceinline__ int32_t chain_next(IdxWalker<INV>& X, int32_t s,
 // in the low half, range scan in the high half).
 template <bool RAM, bool INV, class Emit>
 __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
-                         int32_t start, Emit& emit) {
+                         int32_t start, Emit& emit, uint32_t* steps = nullptr) {
+    // chunks by how each step was decided, one count per lane 0..3 (kept
+    // only when `steps` is given)
+    uint32_t nk = 0;
+    const uint32_t lk = lane_id();
     IdxWalker<INV> X;
-    X.init(J, ws.idx + J.idx0, ws.succ + J.idx0 * kSuccSlots, base);
+    // successor words are built for RAM only: for AE, whose chains meet
+    // within a few chunks, the pass cost as much as it saved
+    X.init(J, ws.idx + J.idx0, RAM ? ws.succ + J.idx0 * kSuccSlots : nullptr, base);
     const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
     // a cut lands 1 byte (RAM) or w + 1 bytes (AE) after its node
     const int32_t delta = RAM ? 1 : w + 1;
@@ -301,7 +290,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     int32_t nt = 0, ns = -1;           // the node of the cut at s (ns < 0: none)
     bool stop = false;
     while (s < X.n && !stop) {
-        if (ns >= 0) {                 // on a node: its successor word
+        if (RAM && ns >= 0) {          // on a node: its successor word
             X.ahead(nt);
             const uint32_t sw = X.succ_word(nt - X.p0, (uint32_t)ns);
             int32_t c;
@@ -314,6 +303,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
                 c = sw == kSuccForced ? s + M : sw == kSuccEnd ? X.n : -1;
             }
             if (c > s && c <= X.n) {   // (always, for words of this pass)
+                nk += lk == 0;
                 if (emit(c)) break;
                 s = c;
                 continue;
@@ -332,6 +322,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
             if (c >= 0) {
                 nt = X.hit_t;
                 ns = X.hit_s;
+                nk += lk == 1;
                 if (emit(c)) break;
                 s = c;
                 continue;
@@ -341,6 +332,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
         if (re >= 0) {
             while (s + w <= re - 1) {
                 const int32_t c = s + w + 1;
+                nk += lk == 2;
                 if (emit(c)) {
                     stop = true;
                     break;
@@ -350,9 +342,11 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
             continue;
         }
         const int32_t c = chain_next<RAM, INV>(X, s, w, M);
+        nk += lk == 3;
         if (emit(c)) break;
         s = c;
     }
+    if (steps != nullptr && lk < 4) steps[lk] = nk;
     return min(X.reads_ebs, 0xFFFFu) | (min(X.reads_rs, 0xFFFFu) << 16);
 }
 
@@ -441,7 +435,7 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
         last = c;
         return c >= b;
     };
-    const uint32_t reads = walk<RAM, INV>(J, ws, a, 0, emit);
+    const uint32_t reads = walk<RAM, INV>(J, ws, a, 0, emit, ws.meta[item].steps);
     out.finish();
     if (lane_id() == 0) {
         SegMeta& m = ws.meta[item];
@@ -579,7 +573,9 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
         m.count = count;
         m.entry = (uint64_t)X;
         m.rexit = (uint64_t)rexit;
-        m.reads += reads;
+        const uint32_t r0 = m.reads;               // two saturating halves
+        m.reads = min((r0 & 0xFFFFu) + (reads & 0xFFFFu), 0xFFFFu) |
+                  (min((r0 >> 16) + (reads >> 16), 0xFFFFu) << 16);
     }
     return rexit;
 }
@@ -636,8 +632,8 @@ __global__ __launch_bounds__(kIdxThreads) void k_index(Plan P, ChainWs ws,
     }
 }
 
-// Successor pass: one workgroup per item, as the index pass.
-template <bool RAM, bool ONE>
+// Successor pass (RAM): one workgroup per item, as the index pass.
+template <bool ONE>
 __global__ __launch_bounds__(kSuccThreads) void k_succ(Plan P, ChainWs ws,
                                                       uint32_t want) {
     __shared__ uint4 pages[kSuccThreads / kWave][kSuccSpan];
@@ -646,14 +642,14 @@ __global__ __launch_bounds__(kSuccThreads) void k_succ(Plan P, ChainWs ws,
         const uint32_t wid = uni(blockIdx.x);
         if (wid >= P.one_items) return;
         const JobView J = view(P.one);
-        if (J.ok && J.algo == want) succ_item<RAM>(J, wid, ws.idx, ws.succ, my);
+        if (J.ok && J.algo == want) succ_item(J, wid, ws.idx, ws.succ, my);
     } else {
         uint32_t first, last;
         item_range(P, want, first, last);
         for (uint32_t wid = first + uni(blockIdx.x); wid < last; wid += gridDim.x) {
             const Item it = P.items[wid];
             const JobView J = view(P.jobs[uni(it.job)]);
-            if (J.ok && J.algo == want) succ_item<RAM>(J, uni(it.seg), ws.idx, ws.succ, my);
+            if (J.ok && J.algo == want) succ_item(J, uni(it.seg), ws.idx, ws.succ, my);
         }
     }
 }
@@ -876,11 +872,10 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
     if (part & kPartSpec) {
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
                    dim3(kIdxThreads), 0, st, P, ws, want);
-        const char* succ_name = RAM ? (ONE ? "successors_ram" : "successors_batch_ram")
-                                : INV ? (ONE ? "successors_ae_min" : "successors_batch_ae_min")
-                                      : (ONE ? "successors_ae" : "successors_batch_ae");
-        CDC_LAUNCH(mk, 1, succ_name, (k_succ<RAM, ONE>), dim3(items_upper),
-                   dim3(kSuccThreads), 0, st, P, ws, want);
+        if (RAM)
+            CDC_LAUNCH(mk, 1, ONE ? "successors_ram" : "successors_batch_ram",
+                       (k_succ<ONE>), dim3(items_upper), dim3(kSuccThreads), 0,
+                       st, P, ws, want);
         CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     }
     if (part & kPartFix)

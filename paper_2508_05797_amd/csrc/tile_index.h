@@ -174,13 +174,15 @@ struct IdxWalker {
     int32_t hit_t, hit_s; // node of the last fast step's cut (tile, slot), or hit_s < 0
     uint32_t reads_ebs, reads_rs;   // tiles whose bytes each pattern read
 
+    // job_succ may be null: the walker then never stands on a node
     __device__ void init(const JobView& J, const uint4* job_idx,
                          const uint32_t* job_succ, int64_t base) {
         src.init(J.data, (uint64_t)J.n);
         t0 = (base + src.shift) >> 10;
         ph = (int32_t)((base + src.shift) & (kTile - 1));
         idx = job_idx + t0;
-        succ = (const uint4*)(job_succ + t0 * kSuccSlots);
+        succ = job_succ != nullptr ? (const uint4*)(job_succ + t0 * kSuccSlots) : nullptr;
+        psa = psb = make_uint4(kSuccUnknown, kSuccUnknown, kSuccUnknown, kSuccUnknown);
         hit_s = -1;
         const int64_t nrel = J.n - base;
         n = (int32_t)min(nrel, (int64_t)0x7FFFF000);
@@ -199,8 +201,10 @@ struct IdxWalker {
     __device__ __forceinline__ void page_load(int32_t q) {
         const int32_t t = min(q + (int32_t)lane_id(), ntiles - 1);
         pf = idx[t];
-        psa = succ[2 * t];
-        psb = succ[2 * t + 1];
+        if (succ != nullptr) {
+            psa = succ[2 * t];
+            psb = succ[2 * t + 1];
+        }
     }
     __device__ __forceinline__ void move_to(int32_t k) {
         const int32_t q = k & ~31;

@@ -103,7 +103,7 @@ def test_noalloc_refuses_beyond_scratch_without_a_device():
                              ctypes.c_void_p(0))
     assert rc == -2
     msg = L.cdc_last_error().decode()
-    assert "scratch" in msg and str(32 << 20) in msg
+    assert "scratch" in msg and str(64 << 20) in msg
     # invalid parameters are refused first
     bad = binding.Params(0, 2, 0, 0)
     assert L.cdc_chunk_noalloc(0, ctypes.byref(bad), fake, 10, fake, fake,

@@ -52,7 +52,7 @@ def test_noalloc_empty_and_refused():
     d = torch.zeros(64, dtype=torch.uint8, device="cuda")
     assert noalloc(d[:0], "ram", 16, 100).numel() == 0
     p = binding.Params(1, 2, 0, 0)
-    n = 1 << 30                                       # w=1: far beyond 32 MiB
+    n = 1 << 30                                       # w=1: far beyond the scratch
     cuts = torch.empty(1, dtype=torch.int64, device="cuda")
     nc = torch.full((1,), -7, dtype=torch.int64, device="cuda")
     rc = binding.lib().cdc_chunk_noalloc(0, ctypes.byref(p),
