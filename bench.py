@@ -190,7 +190,7 @@ def stream_leg(args, binding, datagen, torch, np):
     step_ms = [timed(step, args.steps, torch) for _ in range(REPEATS)]
     ms_step = statistics.median(step_ms)
     # the same chunkings as single calls: per-algorithm whole-call rates
-    per_algo, per_algo_ms, breakdown = {}, {}, {}
+    per_algo, per_algo_ms, breakdown, walk = {}, {}, {}, {}
     for algo, _w in ALGOS:
         ms = [timed(lambda: single(algo), args.steps, torch) for _ in range(REPEATS)]
         per_algo_ms[algo] = spread(ms)
@@ -201,6 +201,8 @@ def stream_leg(args, binding, datagen, torch, np):
         breakdown[algo] = {k: round(v[1] / max(v[0], 1), 4)
                            for k, v in binding.kernel_times().items()}
         binding.set_profiling(0)
+        if algo != "maxp":
+            walk[algo] = binding.walk_stats()
     # HIP events around each call's main kernels on the launch stream
     binding.set_profiling(1)
     binding.kernel_times()
@@ -246,6 +248,7 @@ def stream_leg(args, binding, datagen, torch, np):
     return dict(x=x, value=value, ms_step=ms_step, seq_gbs=seq, roof=roof,
                 step_tuning=step_tuning, step_spread=spread(step_ms),
                 per_algo=per_algo, per_algo_ms=per_algo_ms, breakdown=breakdown,
+                walk=walk,
                 kernel_avg_ms={k: round(v, 4) for k, v in per_kernel.items()},
                 gpu_cuts=gpu_cuts)
 
@@ -281,6 +284,7 @@ def snapshot_leg(args, binding, datagen, torch, np, check):
     out = {"versions": len(versions), "bytes": total, "windows": WIN8K,
            "algorithms": {}}
     devs = [torch.from_numpy(v).cuda() for v in versions]
+    streams = [torch.cuda.Stream() for _ in versions]
     torch.cuda.synchronize()
     for a, w in WIN8K.items():
         room = [binding.max_cuts(v.size, w) for v in versions]
@@ -289,13 +293,28 @@ def snapshot_leg(args, binding, datagen, torch, np, check):
         dgs = [torch.empty((r, 32), dtype=torch.uint8, device="cuda") for r in room]
         table = binding.Dedup(sum(room))
 
+        # the versions are independent: one stream each, forked from and
+        # joined back into the current stream (a version alone holds too
+        # few chunks to fill the device with one hash per lane)
+        def on_streams(work):
+            cur = torch.cuda.current_stream()
+            fork = torch.cuda.Event()
+            fork.record(cur)
+            for st, args_ in zip(streams, work):
+                st.wait_event(fork)
+                yield st, args_
+            for st in streams:
+                j = torch.cuda.Event()
+                j.record(st)
+                cur.wait_event(j)
+
         def chunk_all():
-            for d, c, k in zip(devs, cuts, ncs):
-                binding.chunk_into(d, a, w, MAX_CHUNK, c, k)
+            for st, (d, c, k) in on_streams(zip(devs, cuts, ncs)):
+                binding.chunk_into(d, a, w, MAX_CHUNK, c, k, stream=st)
 
         def fp_all():
-            for d, c, k, g in zip(devs, cuts, ncs, dgs):
-                binding.fingerprint_into(d, c, k, g)
+            for st, (d, c, k, g) in on_streams(zip(devs, cuts, ncs, dgs)):
+                binding.fingerprint_into(d, c, k, g, stream=st)
 
         chunk_all()
         fp_all()
@@ -668,6 +687,12 @@ def main():
         out["per_algorithm_ms"] = s["per_algo_ms"]
         out["kernel_avg_ms"] = s["kernel_avg_ms"]
         out["kernel_breakdown_ms"] = s["breakdown"]
+        out["walk_steps"] = s["walk"]
+        out["walk_steps_note"] = ("RAM / AE speculation chunks by how each was "
+                                  "decided (successor word, fast step from the "
+                                  "tile summaries, run of one value, exact "
+                                  "patterns) and tiles whose bytes the extreme "
+                                  "byte search / range scan read, all passes")
         out["n_cuts"] = {a: int(c.size) for a, c in s["gpu_cuts"].items()}
         out["constant_blocks"] = constant_blocks_leg(args, binding, datagen, torch,
                                                      np, check)

@@ -121,9 +121,10 @@ constexpr uint32_t kSuccSlots = 8;
 // Parallel resolution rounds after the fix-up before the ordered pass.
 constexpr int kRounds = 2;
 
-// Parts of a RAM / AE launch sequence: the speculation pass (streaming over
-// the bytes), the fix-up pass, and the rounds with the settling pass.
-enum : int { kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartAll = 7 };
+// Parts of a RAM / AE launch sequence: the index pass (streaming over the
+// bytes), the successor and speculation passes, the fix-up pass, and the
+// rounds with the settling pass.
+enum : int { kPartIndex = 8, kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartAll = 15 };
 
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,

@@ -181,6 +181,7 @@ __device__ uint32_t succ_of(const SuccPages& G, int32_t u, int32_t P, int32_t w,
 // Successor words of the tiles owned by one segment (as the index pass).
 __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
                           uint32_t* succ, uint4* pg) {
+    if (J.nseg < 2) return;                        // (walked once, without them)
     Source src;
     src.init(J.data, (uint64_t)J.n);
     const int64_t a = (int64_t)seg * J.seg;
@@ -280,9 +281,11 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     uint32_t nk = 0;
     const uint32_t lk = lane_id();
     IdxWalker<INV> X;
-    // successor words are built for RAM only: for AE, whose chains meet
-    // within a few chunks, the pass cost as much as it saved
-    X.init(J, ws.idx + J.idx0, RAM ? ws.succ + J.idx0 * kSuccSlots : nullptr, base);
+    // successor words are built for RAM jobs of several segments only (for
+    // AE, whose chains meet within a few chunks, and for jobs of one
+    // segment, which are walked once, the pass cost as much as it saved)
+    const bool use_succ = RAM && J.nseg > 1;
+    X.init(J, ws.idx + J.idx0, use_succ ? ws.succ + J.idx0 * kSuccSlots : nullptr, base);
     const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
     // a cut lands 1 byte (RAM) or w + 1 bytes (AE) after its node
     const int32_t delta = RAM ? 1 : w + 1;
@@ -290,25 +293,33 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     int32_t nt = 0, ns = -1;           // the node of the cut at s (ns < 0: none)
     bool stop = false;
     while (s < X.n && !stop) {
-        if (RAM && ns >= 0) {          // on a node: its successor word
-            X.ahead(nt);
-            const uint32_t sw = X.succ_word(nt - X.p0, (uint32_t)ns);
-            int32_t c;
-            if (sw < kSuccForced) {
+        if (RAM && ns >= 0) {
+            // on a node: successor words, one lane read per chunk, until a
+            // word names no node
+            uint32_t sw;
+            for (;;) {
+                X.ahead(nt);
+                sw = X.succ_word(nt - X.p0, (uint32_t)ns);
+                if (sw >= kSuccForced) break;
                 nt += (int32_t)(sw >> 23);
                 ns = (int32_t)((sw >> 20) & 7u);
-                c = X.tstart(nt) + (int32_t)(sw & 1023u) + delta;
-            } else {
-                ns = -1;
-                c = sw == kSuccForced ? s + M : sw == kSuccEnd ? X.n : -1;
+                const int32_t c = X.tstart(nt) + (int32_t)(sw & 1023u) + delta;
+                nk += lk == 0;
+                if (emit(c)) {
+                    stop = true;
+                    break;
+                }
+                s = c;
             }
-            if (c > s && c <= X.n) {   // (always, for words of this pass)
+            if (stop) break;
+            ns = -1;
+            const int32_t c = sw == kSuccForced ? s + M : sw == kSuccEnd ? X.n : -1;
+            if (c > s) {
                 nk += lk == 0;
                 if (emit(c)) break;
                 s = c;
                 continue;
             }
-            ns = -1;
         }
         {
             const int32_t L = s + M < X.n ? s + M : X.n;
@@ -321,7 +332,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
             }
             if (c >= 0) {
                 nt = X.hit_t;
-                ns = X.hit_s;
+                ns = use_succ ? X.hit_s : -1;
                 nk += lk == 1;
                 if (emit(c)) break;
                 s = c;
@@ -869,9 +880,10 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
                           const char* spec_name, const char* idx_name, int part) {
     const dim3 blk(kChainThreads), grid((items_upper + kChainWaves - 1) / kChainWaves);
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
-    if (part & kPartSpec) {
+    if (part & kPartIndex)
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
                    dim3(kIdxThreads), 0, st, P, ws, want);
+    if (part & kPartSpec) {
         if (RAM)
             CDC_LAUNCH(mk, 1, ONE ? "successors_ram" : "successors_batch_ram",
                        (k_succ<ONE>), dim3(items_upper), dim3(kSuccThreads), 0,

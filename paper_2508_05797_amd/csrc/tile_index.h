@@ -221,9 +221,14 @@ struct IdxWalker {
     }
     // successor word of slot `slot` of page lane l
     __device__ __forceinline__ uint32_t succ_word(int32_t l, uint32_t slot) const {
-        const uint4 h = slot < 4 ? sa : sb;
-        const uint32_t v = (slot & 2) ? ((slot & 1) ? h.w : h.z) : ((slot & 1) ? h.y : h.x);
-        return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+        // a tree of bitwise selects by the slot's bits (uniform masks): seven
+        // vector operations and no branch
+        const uint32_t m0 = 0u - (slot & 1u), m1 = 0u - ((slot >> 1) & 1u),
+                       m2 = 0u - ((slot >> 2) & 1u);
+        auto sel = [](uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); };
+        const uint32_t lo = sel(m1, sel(m0, sa.w, sa.z), sel(m0, sa.y, sa.x));
+        const uint32_t hi = sel(m1, sel(m0, sb.w, sb.z), sel(m0, sb.y, sb.x));
+        return (uint32_t)__builtin_amdgcn_readlane((int)sel(m2, hi, lo), l);
     }
     // make tile k part of the page
     __device__ __forceinline__ void need(int32_t k) {
