@@ -33,9 +33,14 @@ namespace cdc {
 
 // ------------------------------------------------------------ index pass
 
-// (sixteen waves per item, each with fewer tiles, finish together better
-// than four: 190 against 209 us per GiB on the mixed stream)
-constexpr int kIdxThreads = 1024;                // sixteen waves per item
+// Waves per item of the index pass.  A single call uses sixteen: each wave's
+// share of the segment is smaller, and the waves finish together better
+// than four (190 against 209 us per GiB on the mixed stream).  A batch
+// keeps four: beside the other algorithms' passes, workgroups of sixteen
+// waves made the three-job step slower (0.93 against 0.84 ms).
+template <bool ONE>
+constexpr int idx_threads() { return ONE ? 1024 : 256; }
+constexpr int kIdxThreadsMax = 1024;
 constexpr int kIdxAhead = 4;                     // tile loads in flight per wave
 
 // Summaries of the tiles owned by one segment (those whose first byte lies
@@ -85,7 +90,11 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
 // (AE chains meet within a few chunks of each other, so their walks are
 // short and the same table for AE cost about what it saved; AE walks
 // without it.)
-constexpr int kSuccThreads = 512;                // eight waves, 64 tiles each
+// Waves per item: eight for a single call (54 against 57 us per GiB with
+// four), four in a batch (as the index pass); 64 tiles per wave at a time.
+template <bool ONE>
+constexpr int succ_threads() { return ONE ? 512 : 256; }
+constexpr int kSuccThreadsMax = 512;
 constexpr int kSuccSpan = 2 * kWave;             // tiles a wave sees: its 64 and 64 after
 constexpr int kSuccScan = 8;                     // tiles a range scan may cross
 
@@ -625,9 +634,9 @@ __device__ __forceinline__ void for_items(const Plan& P, uint32_t want, F&& f) {
 
 // Index pass: one workgroup per item (its waves share the item's tiles).
 template <bool INV, bool ONE>
-__global__ __launch_bounds__(kIdxThreads) void k_index(Plan P, ChainWs ws,
+__global__ __launch_bounds__(idx_threads<ONE>()) void k_index(Plan P, ChainWs ws,
                                                        uint32_t want) {
-    __shared__ __align__(16) uint16_t slots[kIdxThreads / kWave][8];
+    __shared__ __align__(16) uint16_t slots[kIdxThreadsMax / kWave][8];
     uint16_t* my = slots[threadIdx.x / kWave];
     if constexpr (ONE) {
         const uint32_t wid = uni(blockIdx.x);
@@ -647,9 +656,9 @@ __global__ __launch_bounds__(kIdxThreads) void k_index(Plan P, ChainWs ws,
 
 // Successor pass (RAM): one workgroup per item, as the index pass.
 template <bool ONE>
-__global__ __launch_bounds__(kSuccThreads) void k_succ(Plan P, ChainWs ws,
+__global__ __launch_bounds__(succ_threads<ONE>()) void k_succ(Plan P, ChainWs ws,
                                                       uint32_t want) {
-    __shared__ uint4 pages[kSuccThreads / kWave][kSuccSpan];
+    __shared__ uint4 pages[kSuccThreadsMax / kWave][kSuccSpan];
     uint4* my = pages[threadIdx.x / kWave];
     if constexpr (ONE) {
         const uint32_t wid = uni(blockIdx.x);
@@ -884,11 +893,11 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     if (part & kPartIndex)
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
-                   dim3(kIdxThreads), 0, st, P, ws, want);
+                   dim3(idx_threads<ONE>()), 0, st, P, ws, want);
     if (part & kPartSpec) {
         if (RAM)
             CDC_LAUNCH(mk, 1, ONE ? "successors_ram" : "successors_batch_ram",
-                       (k_succ<ONE>), dim3(items_upper), dim3(kSuccThreads), 0,
+                       (k_succ<ONE>), dim3(items_upper), dim3(succ_threads<ONE>()), 0,
                        st, P, ws, want);
         CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     }

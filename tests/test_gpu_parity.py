@@ -283,3 +283,30 @@ def test_max_chunk_limit(w):
             assert M in np.diff(np.concatenate([[0], exp.astype(np.int64)]))
     del d
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("algo", ["ram", "ae", "ae_min"])
+def test_walk_stats_account_for_every_chunk(algo):
+    # cdc_walk_stats: the speculation walk of each segment takes every chunk
+    # from the segment's start to the first cut past its end.  On uniform
+    # bytes a speculative chain meets the true one within a few chunks, so
+    # the step kinds add up to the cuts within a few per segment, and no
+    # step is a run of one value; MAXP reports none
+    x = datagen.uniform(16 << 20, 31)
+    d = torch.from_numpy(x).cuda()
+    binding.set_tuning(1 << 20, 0)
+    cuts = binding.chunk(d, algo, 4096, 65536)
+    st = binding.walk_stats()
+    binding.set_tuning(0, 0)
+    exp = oracle.chunk(algo, x, 4096, 65536)
+    assert np.array_equal(cuts.cpu().numpy().astype(np.uint64), exp)
+    assert st["segments"] == 16
+    steps = st["steps_successor"] + st["steps_fast"] + st["steps_run"] + st["steps_exact"]
+    assert abs(steps - exp.size) <= 16 * 4, (steps, exp.size)
+    assert st["steps_run"] == 0
+    if algo != "ram":
+        assert st["steps_successor"] == 0
+    else:
+        assert st["steps_successor"] > 0
+    binding.chunk(d, "maxp", 2048, 65536)
+    assert binding.walk_stats()["segments"] == 0
