@@ -733,6 +733,433 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
     return ex;
 }
 
+// ------------------------------------------------------------ gates (RAM)
+//
+// Runs of whole tiles of one byte value can hold RAM chains apart for good.
+// Inside a run every chunk is w + 1 bytes long.  Where a run of at least
+// max_chunk bytes follows, a chunk that starts in the last w bytes of the
+// run before it ends w + 1 bytes on when the new value is larger (its window
+// holds the new value, which the byte after the window equals) and
+// max_chunk bytes on when it is smaller (nothing before the limit reaches the
+// window's maximum): every chain moves by the same amount, so chains that
+// differ there never meet and no speculative list is landed on.  A run
+// [r0, r1) of at least max_chunk bytes is a gate: a chain has exactly one
+// cut in [r1 - w, r1] (chunks there are w + 1 long, and no chunk jumps the
+// run), at offset phi in that window.  From a gate over the next run of L
+// bytes, phi' = (phi + a) mod (w + 1), with a = -L when the new value is
+// larger or phi = w (the cut is the border itself), else a = max_chunk - L.
+// This pass takes a position known to be on the job's chain (the exit of the
+// segment before the first one whose entry disagrees with it), follows the
+// gates over the tiles after it, and gives every segment start they pass
+// the first cut at or after it as the entry the last round resolves that
+// segment from.  Such entries only save work: the ordered pass still checks
+// every segment against its predecessor.
+constexpr int kGateThreads = 512;
+constexpr int kGatePer = 32;                           // tiles per thread and chunk (at most)
+constexpr int kGateChunk = kGateThreads * kGatePer;    // tiles per chunk (at most)
+constexpr uint32_t kGateList = 2048;                   // run borders kept per chunk
+constexpr uint32_t kGateHeads = 64;                    // starting points per job
+constexpr uint32_t kNotRun = 0x100u;                   // key of a tile of several values
+
+// LDS slot of the key of chunk tile j: one word of padding per 32, so that
+// threads scanning 32 consecutive tiles each fall in different banks
+__device__ __forceinline__ int xsi(int j) { return j + (j >> 5); }
+
+// The job's constants of the gate arithmetic.
+struct GateJob {
+    int64_t w, M, seg, kmax;   // kmax: the last segment
+    double rseg;               // 1 / seg
+    uint32_t W1, Mmod;         // w + 1; max_chunk mod (w + 1)
+    uint32_t smod, smod64;     // seg and 64 seg mod (w + 1)
+    uint32_t h;                // the starting point's segment (entries go after it)
+    bool small;                // 64 (w + 1) < 2^32
+    int64_t shift;             // position of the job's first byte in tile 0
+};
+
+struct GateState {
+    int64_t open;      // first tile of the run not yet closed
+    int64_t g;         // the chain's cut in the last closed run's gate (before
+                       // the first run closes: the starting position)
+    int64_t top;       // highest segment given an entry
+    uint32_t phi;      // offset of g in its gate window
+    uint32_t v, vp;    // key of the open run and of the run before it
+    uint32_t first;    // the open run is the one the start lies in
+    uint32_t stop;
+    uint32_t nb;       // borders of the one-wave first chunk
+};
+
+// floor(x / seg) for 0 <= x < 2^52 (a double estimate, corrected)
+__device__ __forceinline__ int64_t seg_of(const GateJob& G, int64_t x) {
+    int64_t q = (int64_t)((double)x * G.rseg);
+    if (q * G.seg > x) q--;
+    else if ((q + 1) * G.seg <= x) q++;
+    return q;
+}
+
+__device__ __forceinline__ uint32_t mod_w1(uint64_t d, uint32_t W1) {
+    return d >> 32 ? (uint32_t)(d % W1) : (uint32_t)d % W1;
+}
+
+// Entries for segments k, k + step, ... <= k_hi, whose starts lie in a
+// stretch where the chain's cuts are f, f + w + 1, ... (starts at or before
+// f take f); dmod = step * seg mod (w + 1).  One lane's share; returns the
+// last segment written, or -1.
+__device__ int64_t gate_entries(const GateJob& G, SegMeta* M0, int slot, int64_t k,
+                                int64_t k_hi, int64_t step, uint32_t dmod, int64_t f) {
+    int64_t last = -1;
+    const uint32_t W1 = G.W1;
+    uint32_t r = 0;
+    bool have = false;
+    for (; k <= k_hi; k += step) {
+        const int64_t S = k * G.seg;
+        int64_t e = f;
+        if (S > f) {
+            if (!have) {
+                const uint32_t dm = mod_w1((uint64_t)(S - f), W1);
+                r = dm == 0 ? 0 : W1 - dm;
+                have = true;
+            } else {
+                r = r >= dmod ? r - dmod : r + W1 - dmod;
+            }
+            e = S + r;
+        }
+        M0[k - 1].xo[slot] = (uint64_t)e;
+        last = k;
+    }
+    return last;
+}
+
+// Wave 0: close the runs whose ends are the chunk's borders bl[0..nb), in
+// order, while each is a gate.
+__device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
+                           const uint32_t* xs, const uint16_t* bl, uint32_t nb,
+                           GateState& gs) {
+    const uint32_t l = lane_id();
+    const int64_t w = G.w, M = G.M;
+    const uint32_t W1 = G.W1, wu = (uint32_t)w;
+    int64_t open = gs.open, g = gs.g, top = gs.top;
+    uint32_t phi = gs.phi, v = gs.v, vp = gs.vp;
+    bool stop = false;
+    uint32_t i = 0;
+    if (gs.first && nb > 0) {
+        // the run the start lies in ends at the first border: its gate by
+        // steps of w + 1 from the start, and entries for the segments inside
+        const int64_t r1 = (T + bl[0]) * kTile - G.shift;
+        const int64_t E = g, d = r1 - w - E;
+        int64_t g0 = E;
+        if (d > 0) {
+            const uint32_t dm = mod_w1((uint64_t)d, W1);
+            g0 = E + d + (dm == 0 ? 0 : W1 - dm);
+        }
+        const int64_t k_lo = max(seg_of(G, E) + 1, (int64_t)G.h + 1);
+        const int64_t k_hi = min(seg_of(G, g0), G.kmax);
+        int64_t last = -1;
+        if (k_lo <= k_hi)
+            last = gate_entries(G, M0, slot, k_lo + l, k_hi, kWave, G.smod64, E);
+        top = max(top, (int64_t)uni(wave_max((uint32_t)max(last, (int64_t)0))));
+        phi = (uint32_t)(g0 - (r1 - w));
+        g = g0;
+        vp = v;
+        open = T + bl[0];
+        v = xs[xsi(bl[0])];
+        i = 1;
+    }
+    while (i < nb && !stop) {
+        const uint32_t cnt = min(nb - i, (uint32_t)kWave);
+        const bool in = l < cnt;
+        const uint32_t li = in ? l : 0;        // lanes past the batch repeat lane 0
+        const uint32_t bt = bl[i + li];
+        const int64_t b = T + bt;
+        const int64_t bprev = li == 0 ? open : T + bl[i + li - 1];
+        const uint32_t vl = li == 0 ? v : xs[xsi(bl[i + li - 1])];
+        // (every lane takes part in a shuffle: a lane left out reads as 0)
+        const uint32_t vsh = (uint32_t)__shfl((int)vl, (int)(l + kWave - 1) % kWave);
+        const uint32_t vpl = l == 0 ? vp : vsh;
+        const int64_t L = (b - bprev) * kTile;
+        const bool ok = in && vl != kNotRun && L >= M;
+        const bool rise = vl > vpl;
+        const uint32_t Lm = mod_w1((uint64_t)L, W1);
+        const uint32_t ar = Lm == 0 ? 0 : W1 - Lm;             // -L mod (w+1)
+        const uint32_t af = G.Mmod >= Lm ? G.Mmod - Lm : G.Mmod + W1 - Lm;
+        const uint64_t okm = __ballot(ok);
+        const uint32_t lim = ~okm ? min((uint32_t)__builtin_ctzll(~okm), cnt) : cnt;
+        // the phases in order, as a prefix sum of the steps: a lane's step is
+        // ar when its run's value rises, else af, except that a chain whose
+        // cut is the border itself (phase w) steps by ar; such lanes are
+        // rare, and the sum is taken again from the lane after each one
+        const uint32_t A = rise ? ar : af;
+        uint32_t phin = 0, from = 0, base = phi;
+        for (;;) {
+            const uint32_t a0 = l >= from && l < lim ? A : 0u;
+            uint64_t ex_sum;                     // sum of the steps of the lanes before
+            if (G.small) {                       // 64 (w + 1) < 2^32: a 32-bit DPP scan
+                ex_sum = seg_sum<kWave>(a0) - a0;
+            } else {
+                uint64_t x = a0;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const uint64_t y = (uint64_t)__shfl_up((long long)x, (unsigned)o, kWave);
+                    if ((int)l >= o) x += y;
+                }
+                ex_sum = x - a0;
+            }
+            if (l >= from) phin = mod_w1(base + ex_sum, W1);
+            const uint64_t ex = __ballot(l >= from && l < lim && phin == wu && !rise);
+            if (!ex) break;
+            const uint32_t q = (uint32_t)__builtin_ctzll(ex);
+            const uint32_t arq = (uint32_t)__builtin_amdgcn_readlane((int)ar, (int)q);
+            base = wu + arq >= W1 ? wu + arq - W1 : wu + arq;
+            from = q + 1;
+        }
+        if (lim > 0) {
+            // each lane: its run's cuts f, f + w + 1, ... up to its gate
+            const bool step1 = phin == wu || rise;
+            uint32_t pout = phin + (step1 ? ar : af);
+            if (pout >= W1) pout -= W1;
+            phi = (uint32_t)__builtin_amdgcn_readlane((int)pout, (int)lim - 1);
+            const int64_t gout = b * kTile - G.shift - w + pout;
+            const int64_t gsh = (int64_t)__shfl((long long)gout, (int)(l + kWave - 1) % kWave);
+            const int64_t gin = l == 0 ? g : gsh;
+            int64_t last = -1;
+            if (l < lim) {
+                const int64_t k_lo = max(seg_of(G, gin) + 1, (int64_t)G.h + 1);
+                const int64_t k_hi = min(seg_of(G, gout), G.kmax);
+                if (k_lo <= k_hi)
+                    last = gate_entries(G, M0, slot, k_lo, k_hi, 1, G.smod,
+                                        gin + (step1 ? (int64_t)W1 : M));
+            }
+            top = max(top, (int64_t)uni(wave_max((uint32_t)max(last, (int64_t)0))));
+            const int q = (int)lim - 1;
+            g = (int64_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)gout, q) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(gout >> 32), q) << 32));
+            vp = (uint32_t)__builtin_amdgcn_readlane((int)vl, q);
+            const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)bt, q);
+            open = T + bo;
+            v = xs[xsi(bo)];
+        }
+        stop = lim < cnt;
+        i += lim;
+    }
+    if (l == 0) {
+        gs.open = open;
+        gs.g = g;
+        gs.top = top;
+        gs.phi = phi;
+        gs.v = v;
+        gs.vp = vp;
+        gs.first = gs.first && nb == 0;
+        gs.stop = stop;
+    }
+}
+
+// Exclusive prefix sum of one value per thread over the block, in two
+// barriers (a scan per wave, then the waves' totals).
+__device__ uint32_t gate_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
+    const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const uint32_t incl = seg_sum<kWave>(v);
+    if (lane_id() == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (uint32_t k = 0; k < nw; k++) {
+        const uint32_t s = wsum[k];
+        before += k < wv ? s : 0;
+        all += s;
+    }
+    total = all;
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Gate pass over the RAM jobs of several segments, one block per job
+// (grid-stride), before the last round; `slot` is the exit slot that round
+// reads.
+__global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_h,
+                                                        const uint32_t* n_jobs_d,
+                                                        ChainWs ws, int slot) {
+    __shared__ uint32_t xs[kGateChunk + kGateChunk / 32];
+    __shared__ uint16_t bl[kGateList];
+    __shared__ uint32_t wsum[kGateThreads / kWave];
+    __shared__ uint32_t heads[kGateHeads];
+    __shared__ uint32_t n_heads, low_head;
+    __shared__ GateState gs;
+    tail_priority();
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
+    for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
+        __syncthreads();
+        const JobView J = view(P.jobs ? P.jobs[job] : P.one);
+        if (!J.ok || J.algo != kRam || J.nseg < 2 || J.n <= 0) continue;
+        SegMeta* M0 = ws.meta + J.item0;
+        const int64_t shift = (int64_t)((uintptr_t)J.data & 15);
+        const int64_t NT = (J.n + shift + kTile - 1) >> 10;
+        const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);  // word 0 of tile t at 4t
+        auto key_of = [&](int64_t t) -> uint32_t {
+            const uint32_t x = kw[4 * min(t, NT - 1)];
+            return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
+        };
+        // starting points: segments whose entry disagrees with the exit
+        // before them while their predecessor's agrees (that exit then ends
+        // a consistent chain), and whose exit lies in a tile of one value
+        if (tid == 0) {
+            n_heads = 0;
+            low_head = ~0u;
+        }
+        __syncthreads();
+        constexpr uint32_t kHU = 4;              // segments per thread, loads first
+        for (uint32_t k0 = 1; k0 < J.nseg; k0 += kHU * kGateThreads) {
+            uint64_t en[kHU], xa[kHU], eb[kHU], xb[kHU];
+#pragma unroll
+            for (uint32_t u = 0; u < kHU; u++) {
+                const uint32_t k = min(k0 + u * kGateThreads + tid, J.nseg - 1);
+                en[u] = M0[k].entry;
+                xa[u] = M0[k - 1].xo[slot];
+                eb[u] = M0[k - 1].entry;
+                xb[u] = M0[k >= 2 ? k - 2 : 0].xo[slot];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kHU; u++) {
+                const uint32_t k = k0 + u * kGateThreads + tid;
+                if (k < J.nseg && en[u] != xa[u] && (k == 1 || eb[u] == xb[u])) {
+                    const int64_t E = (int64_t)xa[u];
+                    if (E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun) {
+                        atomicMin(&low_head, k);
+                        const uint32_t s = atomicAdd(&n_heads, 1u);
+                        if (s < kGateHeads) heads[s] = k;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t nh = n_heads;
+        if (nh == 0) continue;
+        if (tid == 0) {
+            if (nh > kGateHeads) {               // keep the lowest: its start is exact
+                heads[0] = low_head;
+            } else {
+                for (uint32_t a = 1; a < nh; a++) {          // a few entries
+                    const uint32_t x = heads[a];
+                    uint32_t b = a;
+                    for (; b > 0 && heads[b - 1] > x; b--) heads[b] = heads[b - 1];
+                    heads[b] = x;
+                }
+            }
+        }
+        if (nh > kGateHeads) nh = 1;
+        __syncthreads();
+        // one wave per starting point: a walk goes on past the run the
+        // start lies in only if that run fills the next 64 tiles or the run
+        // after it is of one value too; other starting points are dropped
+        for (uint32_t hi = tid / kWave; hi < nh; hi += kGateThreads / kWave) {
+            const uint32_t l = lane_id();
+            const int64_t E = (int64_t)M0[heads[hi] - 1].xo[slot];
+            const int64_t tE = (E + shift) >> 10;
+            const uint32_t k = key_of(tE + l);
+            const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+            const uint64_t bm = __ballot(k != k0);
+            const bool keep = !bm || (uint32_t)__builtin_amdgcn_readlane(
+                                         (int)k, (int)__builtin_ctzll(bm)) != kNotRun;
+            if (l == 0 && !keep) heads[hi] = 0;
+        }
+        __syncthreads();
+        GateJob G;
+        G.w = J.w;
+        G.M = J.M;
+        G.seg = J.seg;
+        G.kmax = (int64_t)J.nseg - 1;
+        G.rseg = 1.0 / (double)J.seg;
+        G.W1 = (uint32_t)(J.w + 1);
+        G.Mmod = (uint32_t)(J.M % G.W1);
+        G.smod = (uint32_t)((uint64_t)J.seg % G.W1);
+        G.smod64 = (uint32_t)((uint64_t)J.seg * kWave % G.W1);
+        G.shift = shift;
+        G.small = (uint64_t)G.W1 * kWave < (1ull << 32);
+        int64_t covered = 0;
+        for (uint32_t hi = 0; hi < nh; hi++) {
+            const uint32_t h = heads[hi];
+            if (h == 0 || (int64_t)h <= covered) continue;
+            G.h = h;
+            const int64_t E = (int64_t)M0[h - 1].xo[slot];
+            const int64_t tE = (E + shift) >> 10;
+            __syncthreads();
+            if (tid == 0) {
+                gs.open = tE;
+                gs.g = E;
+                gs.top = h;
+                gs.phi = 0;
+                gs.v = key_of(tE);
+                gs.vp = kNotRun;
+                gs.first = 1;
+                gs.stop = 0;
+            }
+            __syncthreads();
+            // the first 64 tiles by one wave (most walks end there), then
+            // chunks of 1, 4 and 16 tiles per thread
+            if (tid < (uint32_t)kWave) {
+                const uint32_t l = lane_id();
+                const uint32_t k = key_of(tE + l);
+                xs[xsi(l)] = k;
+                const uint32_t kp = (uint32_t)__shfl((int)k, (int)(l + kWave - 1) % kWave);
+                const uint32_t pk = l == 0 ? gs.v : kp;
+                const uint64_t bm = __ballot(k == kNotRun || k != pk);
+                const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                if ((bm >> l) & 1u) bl[rk] = (uint16_t)l;
+                const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+                __builtin_amdgcn_wave_barrier();
+                gate_close(G, M0, slot, tE, xs, bl, nb, gs);
+                if (l == 0) gs.nb = nb;
+            }
+            __syncthreads();
+            int64_t T = tE + kWave;
+            bool go = !gs.stop && T < NT;
+            int per = 1;
+            uint32_t kv[kGatePer];
+            auto fetch = [&](int64_t T0, int pr) {      // word 0 of each tile, loads first
+#pragma unroll
+                for (int u = 0; u < kGatePer; u++) {
+                    const int64_t t = T0 + u * kGateThreads + (int64_t)tid;
+                    kv[u] = u < pr ? kw[4 * min(t, NT - 1)] : 0u;
+                }
+            };
+            if (go) fetch(T, per);
+            while (go) {
+                const int C = per * kGateThreads;
+#pragma unroll
+                for (int u = 0; u < kGatePer; u++) {
+                    const int j = u * kGateThreads + (int)tid;
+                    if (u < per)
+                        xs[xsi(j)] = T + j < NT && ie_all(kv[u]) ? ie_max(kv[u]) : kNotRun;
+                }
+                const uint32_t before = gs.v;    // key of tile T - 1 (the open run)
+                __syncthreads();
+                // borders: tiles whose key differs from the tile before
+                const int j0 = (int)tid * per;
+                uint32_t pk = j0 == 0 ? before : xs[xsi(j0 - 1)], bits = 0;
+                for (int u = 0; u < per; u++) {
+                    const uint32_t k = xs[xsi(j0 + u)];
+                    bits |= (uint32_t)(k == kNotRun || k != pk) << u;
+                    pk = k;
+                }
+                uint32_t total;
+                uint32_t at = gate_scan((uint32_t)__builtin_popcount(bits), wsum, total);
+                for (; bits; bits &= bits - 1, at++)
+                    if (at < kGateList) bl[at] = (uint16_t)(j0 + __builtin_ctz(bits));
+                __syncthreads();
+                // the next chunk's loads go out while wave 0 closes this one's runs
+                const int per2 = min(per * 4, kGatePer);
+                if (T + C < NT) fetch(T + C, per2);
+                if (tid < (uint32_t)kWave)
+                    gate_close(G, M0, slot, T, xs, bl, min(total, kGateList), gs);
+                __syncthreads();
+                go = !gs.stop && total <= kGateList && T + C < NT;
+                T += C;
+                per = per2;
+            }
+            covered = gs.top;
+        }
+    }
+}
+
 // Settle one RAM / AE job with the whole block.  A segment is flagged when
 // its entry is not its predecessor's resolved exit.  Each pass takes the
 // heads of the runs of flagged segments (a flagged segment whose predecessor
@@ -886,8 +1313,9 @@ __global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
     } while (0)
 
 template <bool RAM, bool INV, bool ONE>
-static void launch_passes(const Plan& P, uint32_t items_upper,
-                          const ChainWs& ws, hipStream_t st, Marks* mk,
+static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
+                          const uint32_t* n_jobs_d, const ChainWs& ws,
+                          hipStream_t st, Marks* mk,
                           const char* spec_name, const char* idx_name, int part) {
     const dim3 blk(kChainThreads), grid((items_upper + kChainWaves - 1) / kChainWaves);
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
@@ -904,8 +1332,13 @@ static void launch_passes(const Plan& P, uint32_t items_upper,
     if (part & kPartFix)
         CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     if (part & kPartRest)
-        for (int r = 2; r < 2 + kRounds; r++)
+        for (int r = 2; r < 2 + kRounds; r++) {
+            if (RAM && r == 1 + kRounds)         // entries over runs of one value
+                CDC_LAUNCH(mk, 2, "gates", k_gates, dim3(min(jobs_upper, 2048u)),
+                           dim3(kGateThreads), 0, st, P, jobs_upper, n_jobs_d, ws,
+                           (r - 1) & 1);
             CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
+        }
 }
 
 // With one job, items_upper is its segment count (the grid covers every
@@ -916,9 +1349,11 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
                         const ChainWs& ws, hipStream_t st, Marks* mk,
                         const char* spec_name, const char* idx_name, int part) {
     if (P.jobs == nullptr)
-        launch_passes<RAM, INV, true>(P, items_upper, ws, st, mk, spec_name, idx_name, part);
+        launch_passes<RAM, INV, true>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
+                                      spec_name, idx_name, part);
     else
-        launch_passes<RAM, INV, false>(P, items_upper, ws, st, mk, spec_name, idx_name, part);
+        launch_passes<RAM, INV, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
+                                       spec_name, idx_name, part);
     if (part & kPartRest)
         CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
                    dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,

@@ -159,6 +159,38 @@ def test_resolution_rounds(algo, seg):
         binding.set_tuning(0, 0)
 
 
+@pytest.mark.parametrize("seg", [0, 65536, 300000, 1 << 21])
+def test_constant_blocks(seg):
+    """Blocks of one value each, the value changing from block to block: RAM
+    chains keep their distance across every border (each border moves every
+    chain by w + 1 or by max_chunk), so no speculative list is landed on and
+    segment entries come from the runs of one value of at least max_chunk
+    bytes.  Also: the blocks off the tile grid (an unaligned base, 65,000-byte
+    blocks), where the ordered pass settles the job; max_chunk longer than a
+    block; a small window over 4 KiB blocks; such blocks between mixed data;
+    AE and AE-Min."""
+    x = datagen.constant_blocks(1024, 5)                     # 64 MiB
+    try:
+        binding.set_tuning(seg, 0)
+        check(x, "ram", 4096, 65536, tag="blocks seg=%d" % seg)
+        if seg == 0:
+            check(x, "ram", 4096, 65536, offset=5, tag="blocks unaligned")
+            check(x[:16 << 20], "ram", 4096, 131072, tag="blocks M>block")
+            check(datagen.constant_blocks(256, 6, block=65000), "ram", 4096,
+                  65536, tag="blocks 65000")
+            check(datagen.constant_blocks(4096, 7, block=4096), "ram", 100,
+                  1000, tag="blocks 4k")
+            m, _ = datagen.mixed_stream(256, 3)
+            y = np.concatenate([m[:5 << 20], x[:8 << 20], m[5 << 20:11 << 20],
+                                x[8 << 20:12 << 20], m[11 << 20:]])
+            check(y, "ram", 4096, 65536, tag="blocks in mixed")
+            check(y[3:], "ram", 4096, 65536, tag="blocks in mixed, shifted")
+            for algo in ("ae", "ae_min"):
+                check(x, algo, 4096, 65536, tag="blocks")
+    finally:
+        binding.set_tuning(0, 0)
+
+
 def dense_max(n, rate, rng, hi=255, lo_cap=255):
     """Bytes below lo_cap with the value hi planted at the given rate: how
     many of a tile's maxima there are (and whether its summary lists them
