@@ -263,10 +263,16 @@ def constant_blocks_leg(args, binding, datagen, torch, np, check):
     run()
     torch.cuda.synchronize()
     ms = [timed(run, 5, torch) for _ in range(REPEATS)]
+    binding.set_profiling(2)
+    binding.kernel_times()
+    run()
+    breakdown = {k: round(v[1] / max(v[0], 1), 4)
+                 for k, v in binding.kernel_times().items()}
+    binding.set_profiling(0)
     out = {"workload": "RAM w=4096 over 256 MiB of constant 64 KiB blocks, "
                        "value changing per block",
            "gbs": round(x.size / (statistics.median(ms) * 1e-3) / 1e9, 2),
-           "ms": spread(ms)}
+           "ms": spread(ms), "kernel_breakdown_ms": breakdown}
     if check:
         import oracle
         exp = oracle.chunk("ram", x, 4096, MAX_CHUNK)
@@ -621,6 +627,21 @@ def profile_calls(args):
                           "cuts": int(cuts.numel())}), flush=True)
 
 
+def profile_constant_blocks(args):
+    """RAM single calls on the constant-block input alone (for profilers)."""
+    import torch
+    from paper_2508_05797_amd import binding, datagen
+    binding.lib()
+    binding.set_tuning()
+    x = datagen.constant_blocks(CONST_BLOCKS, 5)
+    d = torch.from_numpy(x).to("cuda:0")
+    for _ in range(args.steps):
+        cuts = binding.chunk(d, "ram", 4096, MAX_CHUNK)
+    torch.cuda.synchronize()
+    print(json.dumps({"algorithm": "ram", "input": "constant blocks",
+                      "calls": args.steps, "cuts": int(cuts.numel())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -633,6 +654,9 @@ def main():
                     help="only chunk the 1 GiB stream with single calls of "
                          "each algorithm, --steps times (a short command for "
                          "profilers; prints one line per algorithm)")
+    ap.add_argument("--profile-constant-blocks", action="store_true",
+                    help="only chunk the 256 MiB constant-block input with RAM "
+                         "single calls, --steps times (for profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy kernel three "
                          "times (reference for HBM byte counters)")
@@ -647,6 +671,9 @@ def main():
         return
     if args.profile_calls:
         profile_calls(args)
+        return
+    if args.profile_constant_blocks:
+        profile_constant_blocks(args)
         return
 
     import numpy as np

@@ -152,7 +152,7 @@ std::map<std::pair<int, uintptr_t>, Workspace> g_ws;
 
 static int batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
                     uint64_t bytes_hint, bool side, hipStream_t stream,
-                    uint32_t algo_mask);
+                    uint32_t algo_mask, uint64_t ram_max_n = ~0ull);
 
 namespace {
 
@@ -417,7 +417,8 @@ int enqueue_one(const JobDesc& jd, const Layout& L, void* base, int wpb,
                         wpb, jd.blog != 0, stream, mk);
     } else {
         e = launch_ram_ae(P, jd.nseg, 1, nullptr, chain_ws(base, L), wpb,
-                          stream, mk);
+                          stream, mk,
+                          jd.nseg >= kGateMinSeg ? kPartAll : kPartAll & ~kPartGates);
     }
     if (e != hipSuccess) { set_error("kernel launch", e); return CDC_EHIP; }
     return CDC_OK;
@@ -616,7 +617,8 @@ int cdc_chunk_batch(const cdc_job* jobs, uint32_t n_jobs, hipStream_t stream) {
 // With side = false the algorithms run in order on `stream` (for callers
 // that overlap batches on streams of their own).
 int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-                   bool side, hipStream_t stream, uint32_t algo_mask) {
+                   bool side, hipStream_t stream, uint32_t algo_mask,
+                   uint64_t ram_max_n) {
     t_last_error.clear();
     if (!jobs || n_jobs == 0) {
         t_last_error = "invalid argument";
@@ -624,14 +626,14 @@ int cdc::batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
     }
     std::unique_lock<std::mutex> g(g_mu);
     return batch_on(workspace_for(stream), jobs, n_jobs, bytes_hint, side, stream,
-                    algo_mask);
+                    algo_mask, ram_max_n);
 }
 
 // The batch on workspace `ws` (g_mu held).  Jobs of algorithms outside
 // algo_mask must not occur (their passes are not enqueued).
 int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
                   uint64_t bytes_hint, bool side, hipStream_t stream,
-                  uint32_t algo_mask) {
+                  uint32_t algo_mask, uint64_t ram_max_n) {
     BatchCaps caps = ws.res_caps;
     if (ws.res_jobs < n_jobs) {
         // No reservation covers this batch: read the descriptors back to size
@@ -697,8 +699,11 @@ int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
                            at<uint8_t>(ws.dev, L.bmax), at<int64_t>(ws.dev, L.bpos),
                            cw.err, wpb, caps.blocks != 0, st, mk);
     };
+    // the gate pass only where a RAM job can reach kGateMinSeg segments
+    const int no_gates = ram_max_n > (kGateMinSeg - 1) * caps.seg_chain ? 0 : kPartGates;
     auto chain = [&](uint32_t algo, hipStream_t st, int part) {
-        return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk, part);
+        return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk,
+                            part & ~no_gates);
     };
     const bool has_ram = algo_mask & (1u << kRam), has_ae = algo_mask & (1u << kAe);
     const bool has_min = algo_mask & (1u << kAeMin), has_maxp = algo_mask & (1u << kMaxp);
@@ -714,7 +719,8 @@ int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
         if (e == hipSuccess && has_ram) e = chain(kRam, stream, kPartIndex | kPartSpec);
         if (e == hipSuccess && has_ae) e = chain(kAe, sd.s[0], kPartIndex | kPartSpec);
         if (e == hipSuccess && has_maxp) e = maxp(sd.s[1]);
-        if (e == hipSuccess && has_ram) e = chain(kRam, stream, kPartFix | kPartRest);
+        if (e == hipSuccess && has_ram)
+            e = chain(kRam, stream, kPartFix | kPartRest | kPartGates);
         if (e == hipSuccess && has_ae) e = chain(kAe, sd.s[0], kPartFix | kPartRest);
         if (e == hipSuccess && has_min) e = chain(kAeMin, sd.s[0], kPartAll);
         // the side streams join back even after a failed launch, so that no
@@ -728,8 +734,7 @@ int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
             e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
     } else {
         for (uint32_t a : {kRam, kAe, kAeMin})
-            if (e == hipSuccess && (algo_mask & (1u << a)))
-                e = launch_chain(P, a, grid_waves, n_jobs, nullptr, cw, stream, mk);
+            if (e == hipSuccess && (algo_mask & (1u << a))) e = chain(a, stream, kPartAll);
         if (e == hipSuccess && (has_ram || has_ae || has_min))
             e = launch_emit(P, grid_waves, cw, wpb, stream, mk);
         if (e == hipSuccess && has_maxp) e = maxp(stream);

@@ -124,12 +124,17 @@ constexpr int kRounds = 2;
 // Parts of a RAM / AE launch sequence: the index pass (streaming over the
 // bytes), the successor and speculation passes, the fix-up pass, and the
 // rounds with the settling pass.
-enum : int { kPartIndex = 8, kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartAll = 15 };
+enum : int { kPartIndex = 8, kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartGates = 16,
+             kPartAll = 31 };
+
+// RAM jobs of fewer segments are settled by the fix-up and the two rounds
+// alone; the gate pass (kPartGates, with the rounds) only serves longer ones.
+constexpr uint32_t kGateMinSeg = 2 + kRounds + 1;
 
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int waves_per_block,
-                         hipStream_t st, Marks* marks);
+                         hipStream_t st, Marks* marks, int part = kPartAll);
 // The passes of one algorithm (kRam, kAe or kAeMin), and the output copy of
 // all RAM / AE items (launch_ram_ae is the three and the copy in order).
 hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
@@ -162,9 +167,12 @@ void drop_workspace(hipStream_t st);
 // cdc_chunk_batch with the batch's total length known to the caller (0: not
 // known; the length only sizes the launch grids), the choice of running
 // the algorithms side by side on the workspace's own streams (side) or in
-// order on `stream`, and the algorithms the batch can contain (bit a of
-// algo_mask for algorithm a; the passes of the others are not enqueued).
+// order on `stream`, the algorithms the batch can contain (bit a of
+// algo_mask for algorithm a; the passes of the others are not enqueued),
+// and the length of its longest RAM job when the caller knows it (the gate
+// pass is enqueued only where a RAM job can have kGateMinSeg segments).
 int batch_run(const cdc_job* jobs, uint32_t n_jobs, uint64_t bytes_hint,
-              bool side, hipStream_t stream, uint32_t algo_mask = 0xFu);
+              bool side, hipStream_t stream, uint32_t algo_mask = 0xFu,
+              uint64_t ram_max_n = ~0ull);
 
 }  // namespace cdc

@@ -755,7 +755,7 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
 // segment from.  Such entries only save work: the ordered pass still checks
 // every segment against its predecessor.
 constexpr int kGateThreads = 512;
-constexpr int kGatePer = 32;                           // tiles per thread and chunk (at most)
+constexpr int kGatePer = 16;                           // tiles per thread and chunk (at most)
 constexpr int kGateChunk = kGateThreads * kGatePer;    // tiles per chunk (at most)
 constexpr uint32_t kGateList = 2048;                   // run borders kept per chunk
 constexpr uint32_t kGateHeads = 64;                    // starting points per job
@@ -981,181 +981,200 @@ __global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_
     __shared__ uint32_t wsum[kGateThreads / kWave];
     __shared__ uint32_t heads[kGateHeads];
     __shared__ uint32_t n_heads, low_head;
+    __shared__ uint32_t cand[kGateThreads];
+    __shared__ uint32_t n_cand;
     __shared__ GateState gs;
     tail_priority();
     const uint32_t tid = threadIdx.x;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
-    for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
+    // each block looks at kGateThreads jobs at a time, one per thread, and
+    // works on those that are RAM jobs of several segments
+    for (uint32_t base = blockIdx.x * kGateThreads; base < n_jobs;
+         base += gridDim.x * kGateThreads) {
         __syncthreads();
-        const JobView J = view(P.jobs ? P.jobs[job] : P.one);
-        if (!J.ok || J.algo != kRam || J.nseg < 2 || J.n <= 0) continue;
-        SegMeta* M0 = ws.meta + J.item0;
-        const int64_t shift = (int64_t)((uintptr_t)J.data & 15);
-        const int64_t NT = (J.n + shift + kTile - 1) >> 10;
-        const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);  // word 0 of tile t at 4t
-        auto key_of = [&](int64_t t) -> uint32_t {
-            const uint32_t x = kw[4 * min(t, NT - 1)];
-            return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
-        };
-        // starting points: segments whose entry disagrees with the exit
-        // before them while their predecessor's agrees (that exit then ends
-        // a consistent chain), and whose exit lies in a tile of one value
-        if (tid == 0) {
-            n_heads = 0;
-            low_head = ~0u;
+        if (tid == 0) n_cand = 0;
+        __syncthreads();
+        if (base + tid < n_jobs) {
+            const JobDesc& D = P.jobs ? P.jobs[base + tid] : P.one;
+            if (D.ok && D.algo == kRam && D.nseg >= kGateMinSeg && D.n > 0)
+                cand[atomicAdd(&n_cand, 1u)] = base + tid;
         }
         __syncthreads();
-        constexpr uint32_t kHU = 4;              // segments per thread, loads first
-        for (uint32_t k0 = 1; k0 < J.nseg; k0 += kHU * kGateThreads) {
-            uint64_t en[kHU], xa[kHU], eb[kHU], xb[kHU];
-#pragma unroll
-            for (uint32_t u = 0; u < kHU; u++) {
-                const uint32_t k = min(k0 + u * kGateThreads + tid, J.nseg - 1);
-                en[u] = M0[k].entry;
-                xa[u] = M0[k - 1].xo[slot];
-                eb[u] = M0[k - 1].entry;
-                xb[u] = M0[k >= 2 ? k - 2 : 0].xo[slot];
+        const uint32_t nc = n_cand;
+        for (uint32_t ci = 0; ci < nc; ci++) {
+            const uint32_t job = cand[ci];
+            __syncthreads();
+            const JobView J = view(P.jobs ? P.jobs[job] : P.one);
+            SegMeta* M0 = ws.meta + J.item0;
+            const int64_t shift = (int64_t)((uintptr_t)J.data & 15);
+            const int64_t NT = (J.n + shift + kTile - 1) >> 10;
+            const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);  // word 0 of tile t at 4t
+            auto key_of = [&](int64_t t) -> uint32_t {
+                const uint32_t x = kw[4 * min(t, NT - 1)];
+                return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
+            };
+            // starting points: segments whose entry disagrees with the exit
+            // before them while their predecessor's agrees (that exit then ends
+            // a consistent chain), and whose exit lies in a tile of one value
+            if (tid == 0) {
+                n_heads = 0;
+                low_head = ~0u;
             }
-#pragma unroll
-            for (uint32_t u = 0; u < kHU; u++) {
-                const uint32_t k = k0 + u * kGateThreads + tid;
-                if (k < J.nseg && en[u] != xa[u] && (k == 1 || eb[u] == xb[u])) {
-                    const int64_t E = (int64_t)xa[u];
-                    if (E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun) {
-                        atomicMin(&low_head, k);
-                        const uint32_t s = atomicAdd(&n_heads, 1u);
-                        if (s < kGateHeads) heads[s] = k;
+            __syncthreads();
+            constexpr uint32_t kHU = 4;              // segments per thread, loads first
+            for (uint32_t k0 = 1; k0 < J.nseg; k0 += kHU * kGateThreads) {
+                uint64_t en[kHU], xa[kHU], eb[kHU], xb[kHU];
+    #pragma unroll
+                for (uint32_t u = 0; u < kHU; u++) {
+                    const uint32_t k = min(k0 + u * kGateThreads + tid, J.nseg - 1);
+                    en[u] = M0[k].entry;
+                    xa[u] = M0[k - 1].xo[slot];
+                    eb[u] = M0[k - 1].entry;
+                    xb[u] = M0[k >= 2 ? k - 2 : 0].xo[slot];
+                }
+    #pragma unroll
+                for (uint32_t u = 0; u < kHU; u++) {
+                    const uint32_t k = k0 + u * kGateThreads + tid;
+                    if (k < J.nseg && en[u] != xa[u] && (k == 1 || eb[u] == xb[u])) {
+                        const int64_t E = (int64_t)xa[u];
+                        if (E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun) {
+                            atomicMin(&low_head, k);
+                            const uint32_t s = atomicAdd(&n_heads, 1u);
+                            if (s < kGateHeads) heads[s] = k;
+                        }
                     }
                 }
             }
-        }
-        __syncthreads();
-        uint32_t nh = n_heads;
-        if (nh == 0) continue;
-        if (tid == 0) {
-            if (nh > kGateHeads) {               // keep the lowest: its start is exact
-                heads[0] = low_head;
-            } else {
-                for (uint32_t a = 1; a < nh; a++) {          // a few entries
-                    const uint32_t x = heads[a];
-                    uint32_t b = a;
-                    for (; b > 0 && heads[b - 1] > x; b--) heads[b] = heads[b - 1];
-                    heads[b] = x;
-                }
-            }
-        }
-        if (nh > kGateHeads) nh = 1;
-        __syncthreads();
-        // one wave per starting point: a walk goes on past the run the
-        // start lies in only if that run fills the next 64 tiles or the run
-        // after it is of one value too; other starting points are dropped
-        for (uint32_t hi = tid / kWave; hi < nh; hi += kGateThreads / kWave) {
-            const uint32_t l = lane_id();
-            const int64_t E = (int64_t)M0[heads[hi] - 1].xo[slot];
-            const int64_t tE = (E + shift) >> 10;
-            const uint32_t k = key_of(tE + l);
-            const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
-            const uint64_t bm = __ballot(k != k0);
-            const bool keep = !bm || (uint32_t)__builtin_amdgcn_readlane(
-                                         (int)k, (int)__builtin_ctzll(bm)) != kNotRun;
-            if (l == 0 && !keep) heads[hi] = 0;
-        }
-        __syncthreads();
-        GateJob G;
-        G.w = J.w;
-        G.M = J.M;
-        G.seg = J.seg;
-        G.kmax = (int64_t)J.nseg - 1;
-        G.rseg = 1.0 / (double)J.seg;
-        G.W1 = (uint32_t)(J.w + 1);
-        G.Mmod = (uint32_t)(J.M % G.W1);
-        G.smod = (uint32_t)((uint64_t)J.seg % G.W1);
-        G.smod64 = (uint32_t)((uint64_t)J.seg * kWave % G.W1);
-        G.shift = shift;
-        G.small = (uint64_t)G.W1 * kWave < (1ull << 32);
-        int64_t covered = 0;
-        for (uint32_t hi = 0; hi < nh; hi++) {
-            const uint32_t h = heads[hi];
-            if (h == 0 || (int64_t)h <= covered) continue;
-            G.h = h;
-            const int64_t E = (int64_t)M0[h - 1].xo[slot];
-            const int64_t tE = (E + shift) >> 10;
             __syncthreads();
+            uint32_t nh = n_heads;
+            if (nh == 0) continue;
             if (tid == 0) {
-                gs.open = tE;
-                gs.g = E;
-                gs.top = h;
-                gs.phi = 0;
-                gs.v = key_of(tE);
-                gs.vp = kNotRun;
-                gs.first = 1;
-                gs.stop = 0;
+                if (nh > kGateHeads) {               // keep the lowest: its start is exact
+                    heads[0] = low_head;
+                } else {
+                    for (uint32_t a = 1; a < nh; a++) {          // a few entries
+                        const uint32_t x = heads[a];
+                        uint32_t b = a;
+                        for (; b > 0 && heads[b - 1] > x; b--) heads[b] = heads[b - 1];
+                        heads[b] = x;
+                    }
+                }
             }
+            if (nh > kGateHeads) nh = 1;
             __syncthreads();
-            // the first 64 tiles by one wave (most walks end there), then
-            // chunks of 1, 4 and 16 tiles per thread
-            if (tid < (uint32_t)kWave) {
+            // one wave per starting point: a walk goes on past the run the
+            // start lies in only if that run fills the next 64 tiles or the run
+            // after it is of one value too; other starting points are dropped
+            for (uint32_t hi = tid / kWave; hi < nh; hi += kGateThreads / kWave) {
                 const uint32_t l = lane_id();
+                const int64_t E = (int64_t)M0[heads[hi] - 1].xo[slot];
+                const int64_t tE = (E + shift) >> 10;
                 const uint32_t k = key_of(tE + l);
-                xs[xsi(l)] = k;
-                const uint32_t kp = (uint32_t)__shfl((int)k, (int)(l + kWave - 1) % kWave);
-                const uint32_t pk = l == 0 ? gs.v : kp;
-                const uint64_t bm = __ballot(k == kNotRun || k != pk);
-                const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
-                if ((bm >> l) & 1u) bl[rk] = (uint16_t)l;
-                const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
-                __builtin_amdgcn_wave_barrier();
-                gate_close(G, M0, slot, tE, xs, bl, nb, gs);
-                if (l == 0) gs.nb = nb;
+                const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+                const uint64_t bm = __ballot(k != k0);
+                const bool keep = !bm || (uint32_t)__builtin_amdgcn_readlane(
+                                             (int)k, (int)__builtin_ctzll(bm)) != kNotRun;
+                if (l == 0 && !keep) heads[hi] = 0;
             }
             __syncthreads();
-            int64_t T = tE + kWave;
-            bool go = !gs.stop && T < NT;
-            int per = 1;
-            uint32_t kv[kGatePer];
-            auto fetch = [&](int64_t T0, int pr) {      // word 0 of each tile, loads first
-#pragma unroll
-                for (int u = 0; u < kGatePer; u++) {
-                    const int64_t t = T0 + u * kGateThreads + (int64_t)tid;
-                    kv[u] = u < pr ? kw[4 * min(t, NT - 1)] : 0u;
-                }
-            };
-            if (go) fetch(T, per);
-            while (go) {
-                const int C = per * kGateThreads;
-#pragma unroll
-                for (int u = 0; u < kGatePer; u++) {
-                    const int j = u * kGateThreads + (int)tid;
-                    if (u < per)
-                        xs[xsi(j)] = T + j < NT && ie_all(kv[u]) ? ie_max(kv[u]) : kNotRun;
-                }
-                const uint32_t before = gs.v;    // key of tile T - 1 (the open run)
+            GateJob G;
+            G.w = J.w;
+            G.M = J.M;
+            G.seg = J.seg;
+            G.kmax = (int64_t)J.nseg - 1;
+            G.rseg = 1.0 / (double)J.seg;
+            G.W1 = (uint32_t)(J.w + 1);
+            G.Mmod = (uint32_t)(J.M % G.W1);
+            G.smod = (uint32_t)((uint64_t)J.seg % G.W1);
+            G.smod64 = (uint32_t)((uint64_t)J.seg * kWave % G.W1);
+            G.shift = shift;
+            G.small = (uint64_t)G.W1 * kWave < (1ull << 32);
+            int64_t covered = 0;
+            for (uint32_t hi = 0; hi < nh; hi++) {
+                const uint32_t h = heads[hi];
+                if (h == 0 || (int64_t)h <= covered) continue;
+                G.h = h;
+                const int64_t E = (int64_t)M0[h - 1].xo[slot];
+                const int64_t tE = (E + shift) >> 10;
                 __syncthreads();
-                // borders: tiles whose key differs from the tile before
-                const int j0 = (int)tid * per;
-                uint32_t pk = j0 == 0 ? before : xs[xsi(j0 - 1)], bits = 0;
-                for (int u = 0; u < per; u++) {
-                    const uint32_t k = xs[xsi(j0 + u)];
-                    bits |= (uint32_t)(k == kNotRun || k != pk) << u;
-                    pk = k;
+                if (tid == 0) {
+                    gs.open = tE;
+                    gs.g = E;
+                    gs.top = h;
+                    gs.phi = 0;
+                    gs.v = key_of(tE);
+                    gs.vp = kNotRun;
+                    gs.first = 1;
+                    gs.stop = 0;
                 }
-                uint32_t total;
-                uint32_t at = gate_scan((uint32_t)__builtin_popcount(bits), wsum, total);
-                for (; bits; bits &= bits - 1, at++)
-                    if (at < kGateList) bl[at] = (uint16_t)(j0 + __builtin_ctz(bits));
                 __syncthreads();
-                // the next chunk's loads go out while wave 0 closes this one's runs
-                const int per2 = min(per * 4, kGatePer);
-                if (T + C < NT) fetch(T + C, per2);
-                if (tid < (uint32_t)kWave)
-                    gate_close(G, M0, slot, T, xs, bl, min(total, kGateList), gs);
+                // the first 64 tiles by one wave (most walks end there), then
+                // chunks of 1, 4 and 16 tiles per thread
+                if (tid < (uint32_t)kWave) {
+                    const uint32_t l = lane_id();
+                    const uint32_t k = key_of(tE + l);
+                    xs[xsi(l)] = k;
+                    const uint32_t kp = (uint32_t)__shfl((int)k, (int)(l + kWave - 1) % kWave);
+                    const uint32_t pk = l == 0 ? gs.v : kp;
+                    const uint64_t bm = __ballot(k == kNotRun || k != pk);
+                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                    if ((bm >> l) & 1u) bl[rk] = (uint16_t)l;
+                    const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+                    __builtin_amdgcn_wave_barrier();
+                    gate_close(G, M0, slot, tE, xs, bl, nb, gs);
+                    if (l == 0) gs.nb = nb;
+                }
                 __syncthreads();
-                go = !gs.stop && total <= kGateList && T + C < NT;
-                T += C;
-                per = per2;
+                int64_t T = tE + kWave;
+                bool go = !gs.stop && T < NT;
+                int per = 1;
+                uint32_t kv[kGatePer];
+                auto fetch = [&](int64_t T0, int pr) {      // word 0 of each tile, loads first
+                    const uint32_t* kb = kw + 4 * T0;       // (32-bit offsets from the chunk)
+                    const uint32_t last = (uint32_t)min(NT - 1 - T0, (int64_t)kGateChunk);
+    #pragma unroll
+                    for (int u = 0; u < kGatePer; u++) {
+                        const uint32_t j = min((uint32_t)(u * kGateThreads) + tid, last);
+                        kv[u] = u < pr ? kb[4 * j] : 0u;
+                    }
+                };
+                if (go) fetch(T, per);
+                while (go) {
+                    const int C = per * kGateThreads;
+    #pragma unroll
+                    for (int u = 0; u < kGatePer; u++) {
+                        const int j = u * kGateThreads + (int)tid;
+                        if (u < per)
+                            xs[xsi(j)] = T + j < NT && ie_all(kv[u]) ? ie_max(kv[u]) : kNotRun;
+                    }
+                    const uint32_t before = gs.v;    // key of tile T - 1 (the open run)
+                    __syncthreads();
+                    // borders: tiles whose key differs from the tile before
+                    const int j0 = (int)tid * per;
+                    uint32_t pk = j0 == 0 ? before : xs[xsi(j0 - 1)], bits = 0;
+                    for (int u = 0; u < per; u++) {
+                        const uint32_t k = xs[xsi(j0 + u)];
+                        bits |= (uint32_t)(k == kNotRun || k != pk) << u;
+                        pk = k;
+                    }
+                    uint32_t total;
+                    uint32_t at = gate_scan((uint32_t)__builtin_popcount(bits), wsum, total);
+                    for (; bits; bits &= bits - 1, at++)
+                        if (at < kGateList) bl[at] = (uint16_t)(j0 + __builtin_ctz(bits));
+                    __syncthreads();
+                    // the next chunk's loads go out while wave 0 closes this one's runs
+                    const int per2 = min(per * 4, kGatePer);
+                    if (T + C < NT) fetch(T + C, per2);
+                    if (tid < (uint32_t)kWave)
+                        gate_close(G, M0, slot, T, xs, bl, min(total, kGateList), gs);
+                    __syncthreads();
+                    go = !gs.stop && total <= kGateList && T + C < NT;
+                    T += C;
+                    per = per2;
+                }
+                covered = gs.top;
             }
-            covered = gs.top;
         }
     }
 }
@@ -1333,8 +1352,9 @@ static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upp
         CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     if (part & kPartRest)
         for (int r = 2; r < 2 + kRounds; r++) {
-            if (RAM && r == 1 + kRounds)         // entries over runs of one value
-                CDC_LAUNCH(mk, 2, "gates", k_gates, dim3(min(jobs_upper, 2048u)),
+            if (RAM && r == 1 + kRounds && (part & kPartGates))   // entries over runs of one value
+                CDC_LAUNCH(mk, 2, "gates", k_gates,
+                           dim3(min((jobs_upper + kGateThreads - 1) / kGateThreads, 256u)),
                            dim3(kGateThreads), 0, st, P, jobs_upper, n_jobs_d, ws,
                            (r - 1) & 1);
             CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
@@ -1389,12 +1409,12 @@ hipError_t launch_emit(const Plan& P, uint32_t items_upper, const ChainWs& ws,
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int wpb, hipStream_t st,
-                         Marks* mk) {
+                         Marks* mk, int part) {
     const bool one = P.jobs == nullptr;
     for (uint32_t algo : {kRam, kAe, kAeMin}) {
         if (!one || P.one.algo == algo) {
             const hipError_t e = launch_chain(P, algo, items_upper, jobs_upper,
-                                              n_jobs_d, ws, st, mk);
+                                              n_jobs_d, ws, st, mk, part);
             if (e != hipSuccess) return e;
         }
     }

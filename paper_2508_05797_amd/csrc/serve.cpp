@@ -103,11 +103,12 @@ public:
             j.max_chunk = q.max_chunk;
             j.status = 0;
         }
-        uint64_t total = 0;
+        uint64_t total = 0, ram_max = 0;
         uint32_t mask = 0;
         for (size_t k = 0; k < batch.size(); k++) {
             total += s.host[k].n;
             mask |= 1u << (s.host[k].algo & 3u);
+            if (s.host[k].algo == CDC_RAM) ram_max = std::max<uint64_t>(ram_max, s.host[k].n);
         }
         const size_t bytes = batch.size() * sizeof(cdc_job);
         if (hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice,
@@ -116,7 +117,7 @@ public:
         // batches overlap across slots; within one, the algorithms run in order
         // only the passes of the algorithms the batch holds
         if (cdc::batch_run(s.dev, (uint32_t)batch.size(), total, false, s.stream,
-                           mask) != CDC_OK)
+                           mask, ram_max) != CDC_OK)
             return false;
         if (hipMemcpyAsync(s.host, s.dev, bytes, hipMemcpyDeviceToHost,
                            s.stream) != hipSuccess ||
