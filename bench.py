@@ -278,7 +278,33 @@ def constant_blocks_leg(args, binding, datagen, torch, np, check):
         exp = oracle.chunk("ram", x, 4096, MAX_CHUNK)
         got = cuts[:int(nc.item())].cpu().numpy().astype(np.uint64)
         out["bit_exact_vs_oracle"] = bool(np.array_equal(got, exp))
-    del d
+
+    def variant(data_dev, host):
+        """The same call timed on other bytes or another address."""
+        c = torch.empty(binding.max_cuts(host.size, 4096), dtype=torch.int64, device="cuda")
+        k = torch.empty(1, dtype=torch.int64, device="cuda")
+        f = lambda: binding.chunk_into(data_dev, "ram", 4096, MAX_CHUNK, c, k)
+        f()
+        torch.cuda.synchronize()
+        vm = [timed(f, 2, torch) for _ in range(3)]
+        r = {"gbs": round(host.size / (statistics.median(vm) * 1e-3) / 1e9, 2),
+             "ms": spread(vm)}
+        if check:
+            import oracle
+            r["bit_exact_vs_oracle"] = bool(np.array_equal(
+                c[:int(k.item())].cpu().numpy().astype(np.uint64),
+                oracle.chunk("ram", host, 4096, MAX_CHUNK)))
+        return r
+    # the same blocks 5 bytes off the 1 KiB tile grid of the address
+    buf = torch.zeros(x.size + 64, dtype=torch.uint8, device="cuda")
+    buf[5:5 + x.size] = d
+    out["offset_5_bytes"] = variant(buf[5:5 + x.size], x)
+    del buf
+    # blocks shorter than max_chunk (no run is a gate: settled in order)
+    y = datagen.constant_blocks(CONST_BLOCKS * 65536 // 65000, 6, block=65000)
+    dy = torch.from_numpy(y).cuda()
+    out["blocks_65000_bytes"] = variant(dy, y)
+    del d, dy
     return out
 
 

@@ -755,11 +755,13 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
 // segment from.  Such entries only save work: the ordered pass still checks
 // every segment against its predecessor.
 constexpr int kGateThreads = 512;
-constexpr int kGatePer = 16;                           // tiles per thread and chunk (at most)
+constexpr int kGatePer = 8;                            // tiles per thread and chunk (at most)
 constexpr int kGateChunk = kGateThreads * kGatePer;    // tiles per chunk (at most)
 constexpr uint32_t kGateList = 2048;                   // run borders kept per chunk
 constexpr uint32_t kGateHeads = 64;                    // starting points per job
 constexpr uint32_t kNotRun = 0x100u;                   // key of a tile of several values
+constexpr uint32_t kTwoRun = 0x400u;                   // | offset: a tile of two runs
+constexpr uint32_t kGateTwo = 512;                     // two-run tiles read per chunk
 
 // LDS slot of the key of chunk tile j: one word of padding per 32, so that
 // threads scanning 32 consecutive tiles each fall in different banks
@@ -829,10 +831,11 @@ __device__ int64_t gate_entries(const GateJob& G, SegMeta* M0, int slot, int64_t
     return last;
 }
 
-// Wave 0: close the runs whose ends are the chunk's borders bl[0..nb), in
-// order, while each is a gate.
-__device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
-                           const uint32_t* xs, const uint16_t* bl, uint32_t nb,
+// Wave 0: close the runs whose ends are the chunk's borders, in order, while
+// each is a gate.  Border i lies bl[i] bytes after the chunk's first byte
+// (at job position pos0) and opens a run of key bk[i].
+__device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t pos0,
+                           const uint32_t* bl, const uint16_t* bk, uint32_t nb,
                            GateState& gs) {
     const uint32_t l = lane_id();
     const int64_t w = G.w, M = G.M;
@@ -844,7 +847,7 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
     if (gs.first && nb > 0) {
         // the run the start lies in ends at the first border: its gate by
         // steps of w + 1 from the start, and entries for the segments inside
-        const int64_t r1 = (T + bl[0]) * kTile - G.shift;
+        const int64_t r1 = pos0 + bl[0];
         const int64_t E = g, d = r1 - w - E;
         int64_t g0 = E;
         if (d > 0) {
@@ -860,8 +863,8 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
         phi = (uint32_t)(g0 - (r1 - w));
         g = g0;
         vp = v;
-        open = T + bl[0];
-        v = xs[xsi(bl[0])];
+        open = r1;
+        v = bk[0];
         i = 1;
     }
     while (i < nb && !stop) {
@@ -869,13 +872,13 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
         const bool in = l < cnt;
         const uint32_t li = in ? l : 0;        // lanes past the batch repeat lane 0
         const uint32_t bt = bl[i + li];
-        const int64_t b = T + bt;
-        const int64_t bprev = li == 0 ? open : T + bl[i + li - 1];
-        const uint32_t vl = li == 0 ? v : xs[xsi(bl[i + li - 1])];
+        const int64_t b = pos0 + bt;
+        const int64_t bprev = li == 0 ? open : pos0 + bl[i + li - 1];
+        const uint32_t vl = li == 0 ? v : bk[i + li - 1];
         // (every lane takes part in a shuffle: a lane left out reads as 0)
         const uint32_t vsh = (uint32_t)__shfl((int)vl, (int)(l + kWave - 1) % kWave);
         const uint32_t vpl = l == 0 ? vp : vsh;
-        const int64_t L = (b - bprev) * kTile;
+        const int64_t L = b - bprev;
         const bool ok = in && vl != kNotRun && L >= M;
         const bool rise = vl > vpl;
         const uint32_t Lm = mod_w1((uint64_t)L, W1);
@@ -917,7 +920,7 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
             uint32_t pout = phin + (step1 ? ar : af);
             if (pout >= W1) pout -= W1;
             phi = (uint32_t)__builtin_amdgcn_readlane((int)pout, (int)lim - 1);
-            const int64_t gout = b * kTile - G.shift - w + pout;
+            const int64_t gout = b - w + pout;
             const int64_t gsh = (int64_t)__shfl((long long)gout, (int)(l + kWave - 1) % kWave);
             const int64_t gin = l == 0 ? g : gsh;
             int64_t last = -1;
@@ -934,8 +937,8 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
                           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(gout >> 32), q) << 32));
             vp = (uint32_t)__builtin_amdgcn_readlane((int)vl, q);
             const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)bt, q);
-            open = T + bo;
-            v = xs[xsi(bo)];
+            open = pos0 + bo;
+            v = bk[i + (uint32_t)q];
         }
         stop = lim < cnt;
         i += lim;
@@ -950,6 +953,35 @@ __device__ void gate_close(const GateJob& G, SegMeta* M0, int slot, int64_t T,
         gs.first = gs.first && nb == 0;
         gs.stop = stop;
     }
+}
+
+// Offset p (1..1023) at which a tile (bytes v, 16 per lane) switches from
+// all bytes a to all bytes b, or 0 when its bytes are not so (one wave).
+__device__ uint32_t two_run_split(const uint4 v, uint32_t a, uint32_t b) {
+    const uint32_t ra = a * 0x01010101u, rb = b * 0x01010101u;
+    auto nib = [](uint32_t z) {            // high bit of each byte -> 4 bits
+        return ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) | ((z >> 28) & 8u);
+    };
+    const uint32_t ea = nib(zero_bytes(v.x ^ ra)) | nib(zero_bytes(v.y ^ ra)) << 4 |
+                        nib(zero_bytes(v.z ^ ra)) << 8 | nib(zero_bytes(v.w ^ ra)) << 12;
+    const uint32_t eb = nib(zero_bytes(v.x ^ rb)) | nib(zero_bytes(v.y ^ rb)) << 4 |
+                        nib(zero_bytes(v.z ^ rb)) << 8 | nib(zero_bytes(v.w ^ rb)) << 12;
+    const bool all_a = ea == 0xFFFFu, all_b = eb == 0xFFFFu;
+    // a lane that switches: a on a prefix of its bytes, b on the rest
+    const bool sw = ea != 0 && !all_a && (ea & (ea + 1)) == 0 && eb == (~ea & 0xFFFFu);
+    if (__ballot(!(all_a || all_b || sw))) return 0;
+    const uint64_t ma = __ballot(all_a), ms = __ballot(sw), mb = __ballot(all_b);
+    if (!~ma) return 0;
+    const uint32_t q = (uint32_t)__builtin_ctzll(~ma);        // first lane not all a
+    if (ma != (q == 0 ? 0ull : (~0ull >> (64 - q)))) return 0;
+    uint32_t p = 16 * q, qb = q;
+    if ((ms >> q) & 1u) {
+        p += (uint32_t)__builtin_popcount((uint32_t)__builtin_amdgcn_readlane((int)ea, (int)q));
+        qb = q + 1;
+    }
+    const uint64_t rest = qb >= 64 ? 0ull : (~0ull << qb);
+    if ((mb & rest) != rest) return 0;
+    return p > 0 && p < (uint32_t)kTile ? p : 0;
 }
 
 // Exclusive prefix sum of one value per thread over the block, in two
@@ -970,25 +1002,251 @@ __device__ uint32_t gate_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
     return before + incl - v;
 }
 
-// Gate pass over the RAM jobs of several segments, one block per job
-// (grid-stride), before the last round; `slot` is the exit slot that round
-// reads.
+// The gate pass over one job, by the whole block (shared arrays passed in).
+__device__ void gate_job(const JobView& J, const ChainWs& ws, int slot, uint32_t* xs,
+                         uint32_t* bl, uint16_t* bk, uint16_t* tr, uint32_t* wsum,
+                         uint32_t* heads, uint32_t& n_heads, uint32_t& low_head,
+                         uint32_t& n_tr, GateState& gs) {
+    const uint32_t tid = threadIdx.x;
+    SegMeta* M0 = ws.meta + J.item0;
+    Source src;
+    src.init(J.data, (uint64_t)J.n);
+    const int64_t shift = src.shift;
+    const int64_t NT = (J.n + shift + kTile - 1) >> 10;
+    const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);  // word 0 of tile t at 4t
+    auto key_of = [&](int64_t t) -> uint32_t {
+        const uint32_t x = kw[4 * min(t, NT - 1)];
+        return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
+    };
+    // starting points: segments whose entry disagrees with the exit before
+    // them while their predecessor's agrees (that exit then ends a consistent
+    // chain), and whose exit lies in a tile of one value
+    if (tid == 0) {
+        n_heads = 0;
+        low_head = ~0u;
+    }
+    __syncthreads();
+    constexpr uint32_t kHU = 4;              // segments per thread, loads first
+    for (uint32_t k0 = 1; k0 < J.nseg; k0 += kHU * kGateThreads) {
+        uint64_t en[kHU], xa[kHU], ep[kHU], xp[kHU];
+#pragma unroll
+        for (uint32_t u = 0; u < kHU; u++) {
+            const uint32_t k = min(k0 + u * kGateThreads + tid, J.nseg - 1);
+            en[u] = M0[k].entry;
+            xa[u] = M0[k - 1].xo[slot];
+            ep[u] = M0[k - 1].entry;
+            xp[u] = M0[k >= 2 ? k - 2 : 0].xo[slot];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kHU; u++) {
+            const uint32_t k = k0 + u * kGateThreads + tid;
+            if (k < J.nseg && en[u] != xa[u] && (k == 1 || ep[u] == xp[u])) {
+                const int64_t E = (int64_t)xa[u];
+                if (E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun) {
+                    atomicMin(&low_head, k);
+                    const uint32_t s = atomicAdd(&n_heads, 1u);
+                    if (s < kGateHeads) heads[s] = k;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t nh = n_heads;
+    if (nh == 0) return;
+    if (tid == 0) {
+        if (nh > kGateHeads) {               // keep the lowest: its start is exact
+            heads[0] = low_head;
+        } else {
+            for (uint32_t a = 1; a < nh; a++) {          // a few entries
+                const uint32_t x = heads[a];
+                uint32_t b = a;
+                for (; b > 0 && heads[b - 1] > x; b--) heads[b] = heads[b - 1];
+                heads[b] = x;
+            }
+        }
+    }
+    if (nh > kGateHeads) nh = 1;
+    __syncthreads();
+    // one wave per starting point, which is kept only where runs of one
+    // value fill about a segment after it: 64 tiles sampled across the next
+    // segment's worth of tiles must be nearly all of one value each (a
+    // stretch shorter than a segment gives at most one entry, which the
+    // rounds and the ordered pass find anyway)
+    const int64_t stride = max((int64_t)1, (J.seg >> 10) / kWave);
+    for (uint32_t hi = tid / kWave; hi < nh; hi += kGateThreads / kWave) {
+        const uint32_t l = lane_id();
+        const int64_t E = (int64_t)M0[heads[hi] - 1].xo[slot];
+        const int64_t tE = (E + shift) >> 10;
+        const uint64_t mixed = __ballot(key_of(tE + 1 + (int64_t)l * stride) == kNotRun);
+        if (l == 0 && __builtin_popcountll(mixed) > 8) heads[hi] = 0;
+    }
+    __syncthreads();
+    GateJob G;
+    G.w = J.w;
+    G.M = J.M;
+    G.seg = J.seg;
+    G.kmax = (int64_t)J.nseg - 1;
+    G.rseg = 1.0 / (double)J.seg;
+    G.W1 = (uint32_t)(J.w + 1);
+    G.Mmod = (uint32_t)(J.M % G.W1);
+    G.smod = (uint32_t)((uint64_t)J.seg % G.W1);
+    G.smod64 = (uint32_t)((uint64_t)J.seg * kWave % G.W1);
+    G.shift = shift;
+    G.small = (uint64_t)G.W1 * kWave < (1ull << 32);
+    int64_t covered = 0;
+    for (uint32_t hi = 0; hi < nh; hi++) {
+        const uint32_t h = heads[hi];
+        if (h == 0 || (int64_t)h <= covered) continue;
+        G.h = h;
+        const int64_t E = (int64_t)M0[h - 1].xo[slot];
+        const int64_t tE = (E + shift) >> 10;
+        __syncthreads();
+        if (tid == 0) {
+            gs.open = E;
+            gs.g = E;
+            gs.top = h;
+            gs.phi = 0;
+            gs.v = key_of(tE);
+            gs.vp = kNotRun;
+            gs.first = 1;
+            gs.stop = 0;
+        }
+        __syncthreads();
+        // chunks of 1, 4, then 16 tiles per thread from E's tile on, the next
+        // chunk's loads in flight while wave 0 closes this one's runs
+        int64_t T = tE;
+        int per = 1;
+        uint32_t kv[kGatePer];
+        auto fetch = [&](int64_t T0, int pr) {      // word 0 of each tile, loads first
+            const uint32_t* kb = kw + 4 * T0;       // (32-bit offsets from the chunk)
+            const uint32_t last = (uint32_t)min(NT - 1 - T0, (int64_t)kGateChunk);
+#pragma unroll
+            for (int u = 0; u < kGatePer; u++) {
+                const uint32_t j = min((uint32_t)(u * kGateThreads) + tid, last);
+                kv[u] = u < pr ? kb[4 * j] : 0u;
+            }
+        };
+        fetch(T, per);
+        for (bool go = true; go;) {
+            const int C = per * kGateThreads;
+#pragma unroll
+            for (int u = 0; u < kGatePer; u++) {
+                const int j = u * kGateThreads + (int)tid;
+                if (u < per)
+                    xs[xsi(j)] = T + j < NT && ie_all(kv[u]) ? ie_max(kv[u]) : kNotRun;
+            }
+            if (tid == 0) {
+                xs[xsi(C)] = key_of(T + C);      // the tile after the chunk
+                n_tr = 0;
+            }
+            const uint32_t before = gs.v;        // key of the open run (tile T - 1's end)
+            __syncthreads();
+            // this thread's tiles j0 .. j0 + per - 1 with a neighbour on each side
+            const int j0 = (int)tid * per;
+            uint32_t kk[kGatePer + 2];
+#pragma unroll
+            for (int u = 0; u < kGatePer + 2; u++)
+                kk[u] = u <= per + 1 ? (j0 + u - 1 < 0 ? before : xs[xsi(j0 + u - 1)]) : 0u;
+            // tiles holding two values between two runs of one value each
+            // (a value change off the tile grid): one wave reads each
+            uint32_t two = 0;
+#pragma unroll
+            for (int u = 0; u < kGatePer; u++) {
+                if (u < per && kk[u + 1] == kNotRun && kk[u] != kNotRun &&
+                    kk[u + 2] != kNotRun && kk[u] != kk[u + 2]) {
+                    two |= 1u << u;
+                    const uint32_t s = atomicAdd(&n_tr, 1u);
+                    if (s < kGateTwo) tr[s] = (uint16_t)(j0 + u);
+                }
+            }
+            __syncthreads();
+            const uint32_t ntr = min(n_tr, kGateTwo);
+            if (ntr > 0) {
+                // four tiles per wave at a time, their loads first
+                constexpr uint32_t kTwoAt = 4;
+                const uint32_t nw = kGateThreads / kWave, wv = tid / kWave;
+                for (uint32_t q0 = wv * kTwoAt; q0 < ntr; q0 += nw * kTwoAt) {
+                    uint4 tb[kTwoAt];
+#pragma unroll
+                    for (uint32_t r = 0; r < kTwoAt; r++)
+                        tb[r] = src.load<false>(T + tr[min(q0 + r, ntr - 1)]);
+#pragma unroll
+                    for (uint32_t r = 0; r < kTwoAt; r++) {
+                        if (q0 + r < ntr) {
+                            const int j = tr[q0 + r];
+                            const uint32_t kp = j == 0 ? before : xs[xsi(j - 1)];
+                            const uint32_t p = two_run_split(tb[r], kp, xs[xsi(j + 1)]);
+                            if (lane_id() == 0 && p) xs[xsi(j)] = kTwoRun | p;
+                        }
+                    }
+                }
+                __syncthreads();
+                // the checked tiles, and a neighbour before this thread's first
+#pragma unroll
+                for (int u = 0; u < kGatePer; u++)
+                    if ((two >> u) & 1u) kk[u + 1] = xs[xsi(j0 + u)];
+                if (j0 > 0 && kk[0] == kNotRun) kk[0] = xs[xsi(j0 - 1)];
+            }
+            // borders: a tile of one value unlike the run before it starts a
+            // run at the tile; a tile of two values starts one at its switch;
+            // any other tile ends the walk
+            uint32_t bits = 0, pk = (kk[0] & kTwoRun) ? kk[1] : kk[0];
+#pragma unroll
+            for (int u = 0; u < kGatePer; u++) {
+                if (u < per) {
+                    const uint32_t k = kk[u + 1];
+                    if (k & kTwoRun) {
+                        bits |= 1u << u;
+                        pk = kk[u + 2];
+                    } else {
+                        bits |= (uint32_t)(k == kNotRun || k != pk) << u;
+                        pk = k;
+                    }
+                }
+            }
+            uint32_t total;
+            uint32_t at = gate_scan((uint32_t)__builtin_popcount(bits), wsum, total);
+            for (; bits; bits &= bits - 1, at++) {
+                const int j = j0 + __builtin_ctz(bits);
+                const uint32_t k = xs[xsi(j)];
+                if (at < kGateList) {
+                    bl[at] = (uint32_t)j * kTile + ((k & kTwoRun) ? (k & (kTwoRun - 1)) : 0u);
+                    bk[at] = (uint16_t)((k & kTwoRun) ? xs[xsi(j + 1)] : k);
+                }
+            }
+            __syncthreads();
+            const int per2 = min(per * 4, kGatePer);
+            if (T + C < NT) fetch(T + C, per2);
+            if (tid < (uint32_t)kWave)
+                gate_close(G, M0, slot, T * kTile - shift, bl, bk, min(total, kGateList), gs);
+            __syncthreads();
+            go = !gs.stop && total <= kGateList && T + C < NT;
+            T += C;
+            per = per2;
+        }
+        covered = gs.top;
+    }
+}
+
+// Gate pass over the RAM jobs of kGateMinSeg or more segments, before the
+// last round; `slot` is the exit slot that round reads.  Each block looks
+// at kGateThreads jobs at a time, one per thread, and works on those.
 __global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_h,
                                                         const uint32_t* n_jobs_d,
                                                         ChainWs ws, int slot) {
-    __shared__ uint32_t xs[kGateChunk + kGateChunk / 32];
-    __shared__ uint16_t bl[kGateList];
+    __shared__ uint32_t xs[kGateChunk + 1 + (kGateChunk + 1) / 32 + 1];
+    __shared__ uint32_t bl[kGateList];
+    __shared__ uint16_t bk[kGateList];
+    __shared__ uint16_t tr[kGateTwo];
     __shared__ uint32_t wsum[kGateThreads / kWave];
     __shared__ uint32_t heads[kGateHeads];
-    __shared__ uint32_t n_heads, low_head;
+    __shared__ uint32_t n_heads, low_head, n_tr;
     __shared__ uint32_t cand[kGateThreads];
     __shared__ uint32_t n_cand;
     __shared__ GateState gs;
     tail_priority();
     const uint32_t tid = threadIdx.x;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
-    // each block looks at kGateThreads jobs at a time, one per thread, and
-    // works on those that are RAM jobs of several segments
     for (uint32_t base = blockIdx.x * kGateThreads; base < n_jobs;
          base += gridDim.x * kGateThreads) {
         __syncthreads();
@@ -1005,176 +1263,8 @@ __global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_
             const uint32_t job = cand[ci];
             __syncthreads();
             const JobView J = view(P.jobs ? P.jobs[job] : P.one);
-            SegMeta* M0 = ws.meta + J.item0;
-            const int64_t shift = (int64_t)((uintptr_t)J.data & 15);
-            const int64_t NT = (J.n + shift + kTile - 1) >> 10;
-            const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);  // word 0 of tile t at 4t
-            auto key_of = [&](int64_t t) -> uint32_t {
-                const uint32_t x = kw[4 * min(t, NT - 1)];
-                return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
-            };
-            // starting points: segments whose entry disagrees with the exit
-            // before them while their predecessor's agrees (that exit then ends
-            // a consistent chain), and whose exit lies in a tile of one value
-            if (tid == 0) {
-                n_heads = 0;
-                low_head = ~0u;
-            }
-            __syncthreads();
-            constexpr uint32_t kHU = 4;              // segments per thread, loads first
-            for (uint32_t k0 = 1; k0 < J.nseg; k0 += kHU * kGateThreads) {
-                uint64_t en[kHU], xa[kHU], eb[kHU], xb[kHU];
-    #pragma unroll
-                for (uint32_t u = 0; u < kHU; u++) {
-                    const uint32_t k = min(k0 + u * kGateThreads + tid, J.nseg - 1);
-                    en[u] = M0[k].entry;
-                    xa[u] = M0[k - 1].xo[slot];
-                    eb[u] = M0[k - 1].entry;
-                    xb[u] = M0[k >= 2 ? k - 2 : 0].xo[slot];
-                }
-    #pragma unroll
-                for (uint32_t u = 0; u < kHU; u++) {
-                    const uint32_t k = k0 + u * kGateThreads + tid;
-                    if (k < J.nseg && en[u] != xa[u] && (k == 1 || eb[u] == xb[u])) {
-                        const int64_t E = (int64_t)xa[u];
-                        if (E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun) {
-                            atomicMin(&low_head, k);
-                            const uint32_t s = atomicAdd(&n_heads, 1u);
-                            if (s < kGateHeads) heads[s] = k;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            uint32_t nh = n_heads;
-            if (nh == 0) continue;
-            if (tid == 0) {
-                if (nh > kGateHeads) {               // keep the lowest: its start is exact
-                    heads[0] = low_head;
-                } else {
-                    for (uint32_t a = 1; a < nh; a++) {          // a few entries
-                        const uint32_t x = heads[a];
-                        uint32_t b = a;
-                        for (; b > 0 && heads[b - 1] > x; b--) heads[b] = heads[b - 1];
-                        heads[b] = x;
-                    }
-                }
-            }
-            if (nh > kGateHeads) nh = 1;
-            __syncthreads();
-            // one wave per starting point: a walk goes on past the run the
-            // start lies in only if that run fills the next 64 tiles or the run
-            // after it is of one value too; other starting points are dropped
-            for (uint32_t hi = tid / kWave; hi < nh; hi += kGateThreads / kWave) {
-                const uint32_t l = lane_id();
-                const int64_t E = (int64_t)M0[heads[hi] - 1].xo[slot];
-                const int64_t tE = (E + shift) >> 10;
-                const uint32_t k = key_of(tE + l);
-                const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
-                const uint64_t bm = __ballot(k != k0);
-                const bool keep = !bm || (uint32_t)__builtin_amdgcn_readlane(
-                                             (int)k, (int)__builtin_ctzll(bm)) != kNotRun;
-                if (l == 0 && !keep) heads[hi] = 0;
-            }
-            __syncthreads();
-            GateJob G;
-            G.w = J.w;
-            G.M = J.M;
-            G.seg = J.seg;
-            G.kmax = (int64_t)J.nseg - 1;
-            G.rseg = 1.0 / (double)J.seg;
-            G.W1 = (uint32_t)(J.w + 1);
-            G.Mmod = (uint32_t)(J.M % G.W1);
-            G.smod = (uint32_t)((uint64_t)J.seg % G.W1);
-            G.smod64 = (uint32_t)((uint64_t)J.seg * kWave % G.W1);
-            G.shift = shift;
-            G.small = (uint64_t)G.W1 * kWave < (1ull << 32);
-            int64_t covered = 0;
-            for (uint32_t hi = 0; hi < nh; hi++) {
-                const uint32_t h = heads[hi];
-                if (h == 0 || (int64_t)h <= covered) continue;
-                G.h = h;
-                const int64_t E = (int64_t)M0[h - 1].xo[slot];
-                const int64_t tE = (E + shift) >> 10;
-                __syncthreads();
-                if (tid == 0) {
-                    gs.open = tE;
-                    gs.g = E;
-                    gs.top = h;
-                    gs.phi = 0;
-                    gs.v = key_of(tE);
-                    gs.vp = kNotRun;
-                    gs.first = 1;
-                    gs.stop = 0;
-                }
-                __syncthreads();
-                // the first 64 tiles by one wave (most walks end there), then
-                // chunks of 1, 4 and 16 tiles per thread
-                if (tid < (uint32_t)kWave) {
-                    const uint32_t l = lane_id();
-                    const uint32_t k = key_of(tE + l);
-                    xs[xsi(l)] = k;
-                    const uint32_t kp = (uint32_t)__shfl((int)k, (int)(l + kWave - 1) % kWave);
-                    const uint32_t pk = l == 0 ? gs.v : kp;
-                    const uint64_t bm = __ballot(k == kNotRun || k != pk);
-                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
-                    if ((bm >> l) & 1u) bl[rk] = (uint16_t)l;
-                    const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
-                    __builtin_amdgcn_wave_barrier();
-                    gate_close(G, M0, slot, tE, xs, bl, nb, gs);
-                    if (l == 0) gs.nb = nb;
-                }
-                __syncthreads();
-                int64_t T = tE + kWave;
-                bool go = !gs.stop && T < NT;
-                int per = 1;
-                uint32_t kv[kGatePer];
-                auto fetch = [&](int64_t T0, int pr) {      // word 0 of each tile, loads first
-                    const uint32_t* kb = kw + 4 * T0;       // (32-bit offsets from the chunk)
-                    const uint32_t last = (uint32_t)min(NT - 1 - T0, (int64_t)kGateChunk);
-    #pragma unroll
-                    for (int u = 0; u < kGatePer; u++) {
-                        const uint32_t j = min((uint32_t)(u * kGateThreads) + tid, last);
-                        kv[u] = u < pr ? kb[4 * j] : 0u;
-                    }
-                };
-                if (go) fetch(T, per);
-                while (go) {
-                    const int C = per * kGateThreads;
-    #pragma unroll
-                    for (int u = 0; u < kGatePer; u++) {
-                        const int j = u * kGateThreads + (int)tid;
-                        if (u < per)
-                            xs[xsi(j)] = T + j < NT && ie_all(kv[u]) ? ie_max(kv[u]) : kNotRun;
-                    }
-                    const uint32_t before = gs.v;    // key of tile T - 1 (the open run)
-                    __syncthreads();
-                    // borders: tiles whose key differs from the tile before
-                    const int j0 = (int)tid * per;
-                    uint32_t pk = j0 == 0 ? before : xs[xsi(j0 - 1)], bits = 0;
-                    for (int u = 0; u < per; u++) {
-                        const uint32_t k = xs[xsi(j0 + u)];
-                        bits |= (uint32_t)(k == kNotRun || k != pk) << u;
-                        pk = k;
-                    }
-                    uint32_t total;
-                    uint32_t at = gate_scan((uint32_t)__builtin_popcount(bits), wsum, total);
-                    for (; bits; bits &= bits - 1, at++)
-                        if (at < kGateList) bl[at] = (uint16_t)(j0 + __builtin_ctz(bits));
-                    __syncthreads();
-                    // the next chunk's loads go out while wave 0 closes this one's runs
-                    const int per2 = min(per * 4, kGatePer);
-                    if (T + C < NT) fetch(T + C, per2);
-                    if (tid < (uint32_t)kWave)
-                        gate_close(G, M0, slot, T, xs, bl, min(total, kGateList), gs);
-                    __syncthreads();
-                    go = !gs.stop && total <= kGateList && T + C < NT;
-                    T += C;
-                    per = per2;
-                }
-                covered = gs.top;
-            }
+            gate_job(J, ws, slot, xs, bl, bk, tr, wsum, heads, n_heads, low_head,
+                     n_tr, gs);
         }
     }
 }

@@ -165,10 +165,11 @@ def test_constant_blocks(seg):
     chains keep their distance across every border (each border moves every
     chain by w + 1 or by max_chunk), so no speculative list is landed on and
     segment entries come from the runs of one value of at least max_chunk
-    bytes.  Also: the blocks off the tile grid (an unaligned base, 65,000-byte
-    blocks), where the ordered pass settles the job; max_chunk longer than a
-    block; a small window over 4 KiB blocks; such blocks between mixed data;
-    AE and AE-Min."""
+    bytes.  Also: the blocks off the tile grid (an unaligned base; blocks
+    of 4,133 bytes, whose value changes fall at every offset inside tiles);
+    blocks shorter than max_chunk (65,000 bytes: no gates, the ordered pass
+    settles the job); max_chunk longer than a block; a small window over
+    4 KiB blocks; such blocks between mixed data; AE and AE-Min."""
     x = datagen.constant_blocks(1024, 5)                     # 64 MiB
     try:
         binding.set_tuning(seg, 0)
@@ -180,6 +181,11 @@ def test_constant_blocks(seg):
                   65536, tag="blocks 65000")
             check(datagen.constant_blocks(4096, 7, block=4096), "ram", 100,
                   1000, tag="blocks 4k")
+            # value changes at every offset inside tiles (tiles of two values)
+            check(datagen.constant_blocks(3000, 8, block=4133), "ram", 100,
+                  1000, tag="blocks 4133")
+            check(datagen.constant_blocks(3000, 8, block=4133), "ram", 100,
+                  1000, offset=11, tag="blocks 4133 unaligned")
             m, _ = datagen.mixed_stream(256, 3)
             y = np.concatenate([m[:5 << 20], x[:8 << 20], m[5 << 20:11 << 20],
                                 x[8 << 20:12 << 20], m[11 << 20:]])
