@@ -735,8 +735,8 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
 
 // ------------------------------------------------------------ gates (RAM)
 //
-// Runs of whole tiles of one byte value can hold RAM chains apart for good.
-// Inside a run every chunk is w + 1 bytes long.  Where a run of at least
+// Runs of one byte value can hold RAM chains apart for good.  Inside a run
+// every chunk is w + 1 bytes long.  Where a run of at least
 // max_chunk bytes follows, a chunk that starts in the last w bytes of the
 // run before it ends w + 1 bytes on when the new value is larger (its window
 // holds the new value, which the byte after the window equals) and
@@ -750,10 +750,13 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
 // larger or phi = w (the cut is the border itself), else a = max_chunk - L.
 // This pass takes a position known to be on the job's chain (the exit of the
 // segment before the first one whose entry disagrees with it), follows the
-// gates over the tiles after it, and gives every segment start they pass
-// the first cut at or after it as the entry the last round resolves that
-// segment from.  Such entries only save work: the ordered pass still checks
-// every segment against its predecessor.
+// gates over the runs after it (read from the tile summaries: a tile of one
+// value continues or starts a run; a tile holding the value of the run
+// before and then that of the run after gives the byte where the value
+// changes), and gives every segment start they pass the first cut at or
+// after it as the entry the last round resolves that segment from.  Such
+// entries only save work: the ordered pass still checks every segment
+// against its predecessor.
 constexpr int kGateThreads = 512;
 constexpr int kGatePer = 8;                            // tiles per thread and chunk (at most)
 constexpr int kGateChunk = kGateThreads * kGatePer;    // tiles per chunk (at most)
@@ -779,7 +782,7 @@ struct GateJob {
 };
 
 struct GateState {
-    int64_t open;      // first tile of the run not yet closed
+    int64_t open;      // job position where the run not yet closed starts
     int64_t g;         // the chain's cut in the last closed run's gate (before
                        // the first run closes: the starting position)
     int64_t top;       // highest segment given an entry
@@ -787,7 +790,6 @@ struct GateState {
     uint32_t v, vp;    // key of the open run and of the run before it
     uint32_t first;    // the open run is the one the start lies in
     uint32_t stop;
-    uint32_t nb;       // borders of the one-wave first chunk
 };
 
 // floor(x / seg) for 0 <= x < 2^52 (a double estimate, corrected)
@@ -1002,6 +1004,42 @@ __device__ uint32_t gate_scan(uint32_t v, uint32_t* wsum, uint32_t& total) {
     return before + incl - v;
 }
 
+// Whether the gate pass has work in a job (one wave): a starting point
+// (a segment whose entry disagrees with the exit before it while its
+// predecessor's agrees) whose exit lies in a tile of one value, with runs of
+// one value filling about a segment after it (64 tiles sampled across the
+// next segment's worth of tiles, nearly all of one value each).  Most jobs
+// have none, and are passed over at this cost.
+__device__ bool gate_worth(const JobView& J, const ChainWs& ws, int slot) {
+    const uint32_t l = lane_id();
+    const SegMeta* M0 = ws.meta + J.item0;
+    const int64_t shift = (int64_t)((uintptr_t)J.data & 15);
+    const int64_t NT = (J.n + shift + kTile - 1) >> 10;
+    const uint32_t* kw = (const uint32_t*)(ws.idx + J.idx0);
+    auto key_of = [&](int64_t t) -> uint32_t {
+        const uint32_t x = kw[4 * min(t, NT - 1)];
+        return t < NT && ie_all(x) ? ie_max(x) : kNotRun;
+    };
+    const int64_t stride = max((int64_t)1, (J.seg >> 10) / kWave);
+    for (uint32_t k0 = 1; k0 < J.nseg; k0 += kWave) {
+        const uint32_t k = min(k0 + l, J.nseg - 1);
+        const uint64_t en = M0[k].entry, xa = M0[k - 1].xo[slot];
+        const uint64_t ep = M0[k - 1].entry, xp = M0[k >= 2 ? k - 2 : 0].xo[slot];
+        const int64_t E = (int64_t)xa;
+        const bool head = k0 + l < J.nseg && en != xa && (k == 1 || ep == xp) &&
+                          E >= 0 && E < J.n && key_of((E + shift) >> 10) != kNotRun;
+        for (uint64_t hm = __ballot(head); hm; hm &= hm - 1) {
+            const int q = __builtin_ctzll(hm);
+            const int64_t Eq = (int64_t)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)E, q) |
+                                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(E >> 32), q) << 32));
+            const int64_t tq = (Eq + shift) >> 10;
+            const uint64_t mixed = __ballot(key_of(tq + 1 + (int64_t)l * stride) == kNotRun);
+            if (__builtin_popcountll(mixed) <= 8) return true;
+        }
+    }
+    return false;
+}
+
 // The gate pass over one job, by the whole block (shared arrays passed in).
 __device__ void gate_job(const JobView& J, const ChainWs& ws, int slot, uint32_t* xs,
                          uint32_t* bl, uint16_t* bk, uint16_t* tr, uint32_t* wsum,
@@ -1112,7 +1150,7 @@ __device__ void gate_job(const JobView& J, const ChainWs& ws, int slot, uint32_t
             gs.stop = 0;
         }
         __syncthreads();
-        // chunks of 1, 4, then 16 tiles per thread from E's tile on, the next
+        // chunks of 1, 4, then 8 tiles per thread from E's tile on, the next
         // chunk's loads in flight while wave 0 closes this one's runs
         int64_t T = tE;
         int per = 1;
@@ -1258,9 +1296,20 @@ __global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_
                 cand[atomicAdd(&n_cand, 1u)] = base + tid;
         }
         __syncthreads();
+        // with several candidates, one wave per candidate first: those with
+        // work stay (in place, in order); one or two go to the block at once
         const uint32_t nc = n_cand;
+        if (nc > 2) {
+            for (uint32_t ci = tid / kWave; ci < nc; ci += kGateThreads / kWave) {
+                const JobView J = view(P.jobs ? P.jobs[cand[ci]] : P.one);
+                const bool worth = gate_worth(J, ws, slot);
+                if (lane_id() == 0 && !worth) cand[ci] = ~0u;
+            }
+            __syncthreads();
+        }
         for (uint32_t ci = 0; ci < nc; ci++) {
             const uint32_t job = cand[ci];
+            if (job == ~0u) continue;
             __syncthreads();
             const JobView J = view(P.jobs ? P.jobs[job] : P.one);
             gate_job(J, ws, slot, xs, bl, bk, tr, wsum, heads, n_heads, low_head,

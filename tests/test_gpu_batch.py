@@ -67,6 +67,33 @@ def test_batch_mixed_algorithms():
     assert binding.device_errors() == 0
 
 
+def test_batch_constant_blocks():
+    """Several long RAM jobs of constant 64 KiB blocks (chains that never
+    meet; segment entries from the gate pass, which first checks each job
+    with one wave) beside mixed and small jobs, at aligned and unaligned
+    offsets."""
+    blocks = datagen.constant_blocks(160, 21)                    # 10 MiB
+    mixed, _ = datagen.mixed_stream(96, 22)                      # 6 MiB
+    host = np.concatenate([blocks, mixed, blocks[:4 << 20], np.zeros(64, np.uint8)])
+    b0, m0, c0 = 0, blocks.size, blocks.size + mixed.size
+    offs = np.array([b0, b0 + 7, b0 + (1 << 20), m0, c0, b0 + 65536, m0 + 5,
+                     b0 + 100, c0 + 3, 0], np.int64)
+    sizes = np.array([blocks.size, blocks.size - 7, 8 << 20, mixed.size, 4 << 20,
+                      6 << 20, 1 << 20, 5000, (4 << 20) - 3, 123], np.int64)
+    algos = ["ram", "ram", "ram", "ram", "ram", "ram", "ae", "ram", "ram", "maxp"]
+    windows = [ALGO_W[a] for a in algos]
+    d = torch.from_numpy(host).cuda()
+    binding.set_tuning(524288, 0)
+    try:
+        b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+        say("case batch constant blocks", b.n_jobs, b.total_bytes)
+        b.run()
+        check_batch(b, host, offs, sizes, algos, windows, [65536] * len(sizes))
+    finally:
+        binding.set_tuning(0, 0)
+    assert binding.device_errors() == 0
+
+
 @pytest.mark.parametrize("algo", ["ram", "ae", "maxp", "ae_min"])
 def test_batch_equals_plain(algo):
     host, offs, sizes = make_files(120, 11)
