@@ -757,7 +757,7 @@ __device__ uint64_t block_exscan(uint64_t v, uint64_t* sh, uint64_t& total) {
 // after it as the entry the last round resolves that segment from.  Such
 // entries only save work: the ordered pass still checks every segment
 // against its predecessor.
-constexpr int kGateThreads = 512;
+constexpr int kGateThreads = 1024;
 constexpr int kGatePer = 8;                            // tiles per thread and chunk (at most)
 constexpr int kGateChunk = kGateThreads * kGatePer;    // tiles per chunk (at most)
 constexpr uint32_t kGateList = 2048;                   // run borders kept per chunk
