@@ -267,6 +267,25 @@ __device__ __forceinline__ void put_forced(uint64_t* out, uint64_t& cnt,
 
 constexpr uint32_t kChainChunk = 4096;   // segment counts staged at a time
 constexpr uint32_t kChainThreads = 256;  // threads per block of the chain pass
+constexpr uint32_t kForcedQ = 256;       // runs of forced cuts queued for the block
+
+// t forced cuts s + M, s + 2M, ... at output index `at` on.  The walker only
+// counts them; the whole block writes them where it meets (most of a
+// stream's cuts can be forced ones: one per M bytes without a candidate).
+struct ForcedRun {
+    uint64_t at;
+    int64_t s, t;
+};
+
+// All threads of the block write the queued runs.
+__device__ void write_forced(uint64_t* out, uint64_t room, int64_t M,
+                             const ForcedRun* fq, uint32_t nq) {
+    for (uint32_t r = 0; r < nq; r++) {
+        const ForcedRun f = fq[r];
+        for (int64_t i = threadIdx.x; i < f.t; i += blockDim.x)
+            if (f.at + (uint64_t)i < room) out[f.at + i] = (uint64_t)(f.s + (i + 1) * M);
+    }
+}
 
 // All threads of the block call this; the block stages the segments'
 // candidate counts in LDS (one parallel read per kChainChunk segments, zero
@@ -274,13 +293,29 @@ constexpr uint32_t kChainThreads = 256;  // threads per block of the chain pass
 // lane at a time (the candidates are sparse, so most steps find none).
 __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                                const uint32_t* cand, uint32_t* err,
-                               uint32_t* lds_nc) {
+                               uint32_t* lds_nc, ForcedRun* fq, uint32_t& lds_nq) {
     const int64_t n = J.n, w = J.w, M = J.M;
     const bool walker = threadIdx.x < kWave;
     uint64_t* out = J.cuts;
     const uint64_t room = max_cuts_of(J);
     uint64_t cnt = 0;
     int64_t s = 0;
+    uint32_t nq = 0;                     // queued forced runs (walker)
+    // t forced cuts after s: queued (the wave writes the queue itself when
+    // it is full)
+    auto forced = [&](int64_t s0, int64_t t) {
+        if (t <= 0) return;
+        if (nq == kForcedQ) {
+            for (uint32_t r = 0; r < nq; r++) {
+                uint64_t at = fq[r].at;
+                put_forced(out, at, room, fq[r].s, fq[r].t, M);
+            }
+            nq = 0;
+        }
+        if (lane_id() == 0) fq[nq] = ForcedRun{cnt, s0, t};
+        nq++;
+        cnt += (uint64_t)t;
+    };
     // the nc candidates of segment seg, in order
     auto take = [&](uint32_t seg, uint32_t nc) {
         const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
@@ -303,7 +338,7 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                                  (!valid || (q - qprev - 1) >= M);
                 const uint64_t bb = __ballot(brk);
                 const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
-                put_forced(out, cnt, room, s, (qf - s) / M, M);
+                forced(s, (qf - s) / M);
                 if (lane_id() >= f && lane_id() < g &&
                     cnt + (lane_id() - f) < room)
                     out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
@@ -343,14 +378,22 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                 if (c3) take(seg + 3, c3);
             }
         }
-        __syncthreads();                 // lds_nc is refilled next
+        if (walker && lane_id() == 0) lds_nq = nq;
+        __syncthreads();
+        write_forced(out, room, M, fq, lds_nq);
+        nq = 0;
+        __syncthreads();                 // lds_nc and the queue are refilled next
     }
-    if (!walker) return;
-    if (n > 0) {
-        put_forced(out, cnt, room, s, (n - s - 1) / M, M);
+    if (walker && n > 0) {
+        forced(s, (n - s - 1) / M);
         if (lane_id() == 0 && cnt < room) out[cnt] = (uint64_t)n;
         cnt++;
     }
+    if (walker && lane_id() == 0) lds_nq = nq;
+    __syncthreads();
+    write_forced(out, room, M, fq, lds_nq);
+    __syncthreads();                     // the queue is reused by the next job
+    if (!walker) return;
     if (cnt > room) {   // cannot happen for a correct chain
         if (lane_id() == 0) atomicOr(err, kErrOverflow);
         cnt = room;
@@ -365,11 +408,13 @@ __global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n
                                                     uint32_t* err) {
     tail_priority();
     __shared__ __align__(16) uint32_t nc[kChainChunk];   // read four at a time
+    __shared__ ForcedRun fq[kForcedQ];
+    __shared__ uint32_t nq;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
         const JobView J = view(P.jobs ? P.jobs[job] : P.one);
         if (!J.ok || J.algo != kMaxp || J.n == 0) continue;   // alike for the block
-        maxp_chain_job(J, meta, cand, err, nc);
+        maxp_chain_job(J, meta, cand, err, nc, fq, nq);
     }
 }
 
