@@ -186,6 +186,12 @@ def test_constant_blocks(seg):
                   1000, tag="blocks 4133")
             check(datagen.constant_blocks(3000, 8, block=4133), "ram", 100,
                   1000, offset=11, tag="blocks 4133 unaligned")
+            # extreme windows: w = 1, w = max_chunk - 1 (every chunk w + 1
+            # long), w close to max_chunk, and a small max_chunk
+            small = x[:8 << 20]
+            for w_, M_ in ((1, 65536), (4096, 4097), (60000, 65536), (100, 101),
+                           (2000, 2048)):
+                check(small, "ram", w_, M_, tag="blocks w=%d M=%d" % (w_, M_))
             m, _ = datagen.mixed_stream(256, 3)
             y = np.concatenate([m[:5 << 20], x[:8 << 20], m[5 << 20:11 << 20],
                                 x[8 << 20:12 << 20], m[11 << 20:]])
