@@ -79,17 +79,15 @@ __device__ void index_item(const JobView& J, uint32_t seg, uint4* idx,
 
 // ------------------------------------------------------------ successor pass
 
-// Each stored position P of a tile's maximum is a possible RAM chain node:
-// a cut lands right after a byte at or above its window's maximum, and
-// where the summaries decide a step that byte is its tile's maximum.  This
-// pass works out, from the summaries alone, where the chain goes from every
-// node: the node of the next cut, a forced cut (the chunk reaches
+// Each stored position P of a tile's maximum is a possible chain node: for
+// RAM, the byte a cut lands right after (it is at or above its window's
+// maximum, and where the summaries decide a step that byte is its tile's
+// maximum); for AE, a final target (the cut lands w + 1 bytes after it).
+// This pass works out, from the summaries alone, where the chain goes from
+// every node: the node of the next cut, a forced cut (the chunk reaches
 // max_chunk), the job's end, or "unknown" where the summaries cannot decide.
 // A walker standing on a node then takes the step as one lookup; on
 // "unknown" it takes the step itself.  Every answer recorded here is exact.
-// (AE chains meet within a few chunks of each other, so their walks are
-// short and the same table for AE cost about what it saved; AE walks
-// without it.)
 // Waves per item: eight for a single call (54 against 57 us per GiB with
 // four), four in a batch (as the index pass); 64 tiles per wave at a time.
 template <bool ONE>
@@ -172,24 +170,48 @@ struct SuccPages {
     }
 };
 
-// Successor word of the RAM node at page position P in page tile u: the
-// chunk that starts right after P.
+// Successor word of the node at page position P in page tile u: the node
+// that ends the chunk starting right after P (RAM) or w + 1 bytes after P
+// (AE).
+template <bool RAM>
 __device__ uint32_t succ_of(const SuccPages& G, int32_t u, int32_t P, int32_t w,
                             int32_t M) {
     const int32_t n = G.n;
     int32_t k;
     uint32_t slot, off;
-    const int32_t c = P + 1, L = min(c + M, n);
-    if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
-    const int32_t T = G.range_max(c, c + w);
-    if (T <= 0) return kSuccUnknown;
-    const int r = G.first_geq(c + w, L, (uint32_t)T, k, slot, off);
-    if (r < 0) return kSuccUnknown;
-    if (r == 0) return L == n ? kSuccEnd : kSuccForced;
+    if constexpr (RAM) {
+        const int32_t c = P + 1, L = min(c + M, n);
+        if (c + w >= L) return L == n ? kSuccEnd : kSuccUnknown;
+        const int32_t T = G.range_max(c, c + w);
+        if (T <= 0) return kSuccUnknown;
+        const int r = G.first_geq(c + w, L, (uint32_t)T, k, slot, off);
+        if (r < 0) return kSuccUnknown;
+        if (r == 0) return L == n ? kSuccEnd : kSuccForced;
+    } else {
+        // the target: the first occurrence p of the largest byte V of
+        // [c, c + w], final when no byte of (c + w, p + w] exceeds V
+        const int32_t c = P + w + 1;
+        if (c >= n) return kSuccUnknown;
+        const int32_t L = min(c + M, n), hi = min(c + w + 1, L);
+        const int32_t V = G.range_max(c, hi);
+        if (V <= 0) return kSuccUnknown;
+        if (G.first_geq(c, hi, (uint32_t)V, k, slot, off) != 1) return kSuccUnknown;
+        const int32_t p = G.ts(k) + (int32_t)off;
+        const int32_t nhi = min(p + w + 1, L);
+        if (V < 255 && nhi > hi) {
+            // (whole tiles, so bytes before hi, none above V, count too)
+            const int32_t k1 = G.tile(nhi - 1);
+            if (!G.has(k1)) return kSuccUnknown;
+            for (int32_t j = G.tile(hi); j <= k1; j++)
+                if ((int32_t)ie_max(G.word0(j)) > V) return kSuccUnknown;
+        }
+        if (p + w >= L) return L == n ? kSuccEnd : kSuccForced;
+    }
     return (uint32_t)(k - u) << 23 | slot << 20 | off;
 }
 
 // Successor words of the tiles owned by one segment (as the index pass).
+template <bool RAM>
 __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
                           uint32_t* succ, uint4* pg) {
     if (J.nseg < 2) return;                        // (walked once, without them)
@@ -229,7 +251,7 @@ __device__ void succ_item(const JobView& J, uint32_t seg, const uint4* idx,
                 if (i >= cnt) break;
                 const uint32_t word = i == 0 ? E.x : i <= 2 ? E.y : i <= 4 ? E.z : E.w;
                 const uint32_t pos = i == 0 ? word >> 16 : (i & 1) ? word & 0xFFFFu : word >> 16;
-                const uint32_t r = succ_of(G, l, SuccPages::ts(l) + (int32_t)pos, w, M);
+                const uint32_t r = succ_of<RAM>(G, l, SuccPages::ts(l) + (int32_t)pos, w, M);
 #pragma unroll
                 for (int j = 0; j < kIdxPos; j++) o[j] = (uint32_t)j == i ? r : o[j];
             }
@@ -292,10 +314,9 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     uint32_t nk = 0;
     const uint32_t lk = lane_id();
     IdxWalker<INV> X;
-    // successor words are built for RAM jobs of several segments only (for
-    // AE, whose chains meet within a few chunks, and for jobs of one
-    // segment, which are walked once, the pass cost as much as it saved)
-    const bool use_succ = RAM && J.nseg > 1;
+    // successor words are built for jobs of several segments only (a job of
+    // one segment is walked once, and the pass cost as much as it saved)
+    const bool use_succ = J.nseg > 1;
     X.init(J, ws.idx + J.idx0, use_succ ? ws.succ + J.idx0 * kSuccSlots : nullptr, base);
     const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
     // a cut lands 1 byte (RAM) or w + 1 bytes (AE) after its node
@@ -304,7 +325,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     int32_t nt = 0, ns = -1;           // the node of the cut at s (ns < 0: none)
     bool stop = false;
     while (s < X.n && !stop) {
-        if (RAM && ns >= 0) {
+        if (ns >= 0) {
             // on a node: successor words, one lane read per chunk, until a
             // word names no node
             uint32_t sw;
@@ -654,8 +675,8 @@ __global__ __launch_bounds__(idx_threads<ONE>()) void k_index(Plan P, ChainWs ws
     }
 }
 
-// Successor pass (RAM): one workgroup per item, as the index pass.
-template <bool ONE>
+// Successor pass: one workgroup per item, as the index pass.
+template <bool RAM, bool ONE>
 __global__ __launch_bounds__(succ_threads<ONE>()) void k_succ(Plan P, ChainWs ws,
                                                       uint32_t want) {
     __shared__ uint4 pages[kSuccThreadsMax / kWave][kSuccSpan];
@@ -664,14 +685,14 @@ __global__ __launch_bounds__(succ_threads<ONE>()) void k_succ(Plan P, ChainWs ws
         const uint32_t wid = uni(blockIdx.x);
         if (wid >= P.one_items) return;
         const JobView J = view(P.one);
-        if (J.ok && J.algo == want) succ_item(J, wid, ws.idx, ws.succ, my);
+        if (J.ok && J.algo == want) succ_item<RAM>(J, wid, ws.idx, ws.succ, my);
     } else {
         uint32_t first, last;
         item_range(P, want, first, last);
         for (uint32_t wid = first + uni(blockIdx.x); wid < last; wid += gridDim.x) {
             const Item it = P.items[wid];
             const JobView J = view(P.jobs[uni(it.job)]);
-            if (J.ok && J.algo == want) succ_item(J, uni(it.seg), ws.idx, ws.succ, my);
+            if (J.ok && J.algo == want) succ_item<RAM>(J, uni(it.seg), ws.idx, ws.succ, my);
         }
     }
 }
@@ -1477,14 +1498,15 @@ static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upp
                           const char* spec_name, const char* idx_name, int part) {
     const dim3 blk(kChainThreads), grid((items_upper + kChainWaves - 1) / kChainWaves);
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
+    const char* succ_name = RAM ? (ONE ? "successors_ram" : "successors_batch_ram")
+                            : INV ? (ONE ? "successors_ae_min" : "successors_batch_ae_min")
+                                  : (ONE ? "successors_ae" : "successors_batch_ae");
     if (part & kPartIndex)
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
                    dim3(idx_threads<ONE>()), 0, st, P, ws, want);
     if (part & kPartSpec) {
-        if (RAM)
-            CDC_LAUNCH(mk, 1, ONE ? "successors_ram" : "successors_batch_ram",
-                       (k_succ<ONE>), dim3(items_upper), dim3(succ_threads<ONE>()), 0,
-                       st, P, ws, want);
+        CDC_LAUNCH(mk, 1, succ_name, (k_succ<RAM, ONE>), dim3(items_upper),
+                   dim3(succ_threads<ONE>()), 0, st, P, ws, want);
         CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
     }
     if (part & kPartFix)
