@@ -293,6 +293,7 @@ BatchCaps batch_caps(uint64_t T, uint64_t J, uint64_t wmin, uint64_t mmax) {
     const uint64_t it_chain = T / c.seg_chain + J;
     const uint64_t it_maxp = T / c.seg_maxp + J;
     c.items = std::max(it_chain, it_maxp);
+    c.items_chain = it_chain;
     auto slot_bound = [&](uint64_t S, uint64_t extra) {
         const uint64_t A = (S + extra) / (wmin + 1) + 2;
         const uint64_t per_item = (T / S + J) * A;
@@ -701,9 +702,14 @@ int cdc::batch_on(Workspace& ws, const cdc_job* jobs, uint32_t n_jobs,
     };
     // the gate pass only where a RAM job can reach kGateMinSeg segments
     const int no_gates = ram_max_n > (kGateMinSeg - 1) * caps.seg_chain ? 0 : kPartGates;
+    const uint64_t chain_items =
+        bytes_hint > 0 ? std::min(caps.items_chain,
+                                  batch_caps(bytes_hint, n_jobs, 1, 2).items_chain)
+                       : caps.items_chain;
+    const bool ae_succ = chain_items <= kAeSuccItems;
     auto chain = [&](uint32_t algo, hipStream_t st, int part) {
         return launch_chain(P, algo, grid_waves, n_jobs, nullptr, cw, st, mk,
-                            part & ~no_gates);
+                            part & ~no_gates, ae_succ);
     };
     const bool has_ram = algo_mask & (1u << kRam), has_ae = algo_mask & (1u << kAe);
     const bool has_min = algo_mask & (1u << kAeMin), has_maxp = algo_mask & (1u << kMaxp);

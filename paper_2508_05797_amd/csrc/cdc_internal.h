@@ -92,6 +92,7 @@ enum : uint32_t { kErrOverflow = 1u };
 // Capacity of a batch workspace and the planning constants.
 struct BatchCaps {
     uint64_t items, slots, blocks, tiles;
+    uint64_t items_chain;    // items of RAM / AE jobs (chain segments + jobs)
     uint64_t seg_chain, seg_maxp;
     uint64_t max_chunk_limit;
 };
@@ -131,6 +132,12 @@ enum : int { kPartIndex = 8, kPartSpec = 1, kPartFix = 2, kPartRest = 4, kPartGa
 // alone; the gate pass (kPartGates, with the rounds) only serves longer ones.
 constexpr uint32_t kGateMinSeg = 2 + kRounds + 1;
 
+// A batch whose RAM / AE items can exceed this count runs AE and AE-Min
+// without successor words: their walkers then hold half the registers, and
+// with many short jobs in flight that occupancy is worth more than the
+// words (launch_chain's ae_succ).
+constexpr uint64_t kAeSuccItems = 8192;
+
 hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
                          uint32_t jobs_upper, const uint32_t* n_jobs_d,
                          const ChainWs& ws, int waves_per_block,
@@ -140,7 +147,7 @@ hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
 hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
                         const ChainWs& ws, hipStream_t st, Marks* marks,
-                        int part = kPartAll);
+                        int part = kPartAll, bool ae_succ = true);
 hipError_t launch_emit(const Plan& P, uint32_t items_upper, const ChainWs& ws,
                        int waves_per_block, hipStream_t st, Marks* marks);
 hipError_t launch_maxp(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,

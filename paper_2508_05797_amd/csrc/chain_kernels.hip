@@ -306,7 +306,7 @@ __device__ __forceinline__ int32_t chain_next(IdxWalker<INV>& X, int32_t s,
 // its window exceeds the first byte), so those ends follow without queries.
 // Returns the tiles whose bytes the two patterns read (extreme byte search
 // in the low half, range scan in the high half).
-template <bool RAM, bool INV, class Emit>
+template <bool RAM, bool INV, bool SUCC, class Emit>
 __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
                          int32_t start, Emit& emit, uint32_t* steps = nullptr) {
     // chunks by how each step was decided, one count per lane 0..3 (kept
@@ -315,8 +315,9 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     const uint32_t lk = lane_id();
     IdxWalker<INV> X;
     // successor words are built for jobs of several segments only (a job of
-    // one segment is walked once, and the pass cost as much as it saved)
-    const bool use_succ = J.nseg > 1;
+    // one segment is walked once, and the pass cost as much as it saved),
+    // and for AE only where the launch asks for them (SUCC)
+    const bool use_succ = SUCC && J.nseg > 1;
     X.init(J, ws.idx + J.idx0, use_succ ? ws.succ + J.idx0 * kSuccSlots : nullptr, base);
     const int32_t w = (int32_t)J.w, M = (int32_t)J.M;
     // a cut lands 1 byte (RAM) or w + 1 bytes (AE) after its node
@@ -325,7 +326,7 @@ __device__ uint32_t walk(const JobView& J, const ChainWs& ws, int64_t base,
     int32_t nt = 0, ns = -1;           // the node of the cut at s (ns < 0: none)
     bool stop = false;
     while (s < X.n && !stop) {
-        if (ns >= 0) {
+        if (SUCC && ns >= 0) {
             // on a node: successor words, one lane read per chunk, until a
             // word names no node
             uint32_t sw;
@@ -465,7 +466,7 @@ __device__ __forceinline__ uint32_t* list_of(const JobView& J,
 
 // ------------------------------------------------------------ speculate
 
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool SUCC>
 __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
                           const ChainWs& ws) {
     const int64_t a = (int64_t)seg * J.seg;
@@ -478,7 +479,7 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
         last = c;
         return c >= b;
     };
-    const uint32_t reads = walk<RAM, INV>(J, ws, a, 0, emit, ws.meta[item].steps);
+    const uint32_t reads = walk<RAM, INV, SUCC>(J, ws, a, 0, emit, ws.meta[item].steps);
     out.finish();
     if (lane_id() == 0) {
         SegMeta& m = ws.meta[item];
@@ -496,7 +497,7 @@ __device__ void speculate(const JobView& J, uint32_t seg, uint32_t item,
 // the cuts before that are written to the fix-up list (fix-up round) or the
 // re-walk list.  Records the resolution (entry, pieces, count, exit) and
 // returns its exit.  One wave.
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool SUCC>
 __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
                                 int64_t X, bool fixup, const ChainWs& ws) {
     const int64_t a = (int64_t)seg * J.seg;
@@ -602,7 +603,7 @@ __device__ int64_t resolve_from(const JobView& J, uint32_t seg, uint32_t item,
             }
             return false;
         };
-        reads = walk<RAM, INV>(J, ws, a, e, emit);
+        reads = walk<RAM, INV, SUCC>(J, ws, a, e, emit);
         wl.finish();
         new_nfix = min(wl.n, J.cap);
     }
@@ -697,30 +698,30 @@ __global__ __launch_bounds__(succ_threads<ONE>()) void k_succ(Plan P, ChainWs ws
     }
 }
 
-template <bool RAM, bool INV, bool ONE>
+template <bool RAM, bool INV, bool ONE, bool SUCC>
 __global__ __launch_bounds__(kChainThreads) void k_spec(Plan P, ChainWs ws) {
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
-        speculate<RAM, INV>(J, seg, wid, ws);
+        speculate<RAM, INV, SUCC>(J, seg, wid, ws);
     });
 }
 
 // Fix-up round: every segment from the previous segment's speculative exit
 // (segment 0 from the job start).
-template <bool RAM, bool INV, bool ONE>
+template <bool RAM, bool INV, bool ONE, bool SUCC>
 __global__ __launch_bounds__(kChainThreads) void k_fix(Plan P, ChainWs ws) {
     tail_priority();
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     for_items<ONE>(P, want, [&](const JobView& J, uint32_t seg, uint32_t wid) {
         const int64_t X = seg == 0 ? 0 : uni64((int64_t)ws.meta[wid - 1].exit);
-        const int64_t h = resolve_from<RAM, INV>(J, seg, wid, X, true, ws);
+        const int64_t h = resolve_from<RAM, INV, SUCC>(J, seg, wid, X, true, ws);
         if (lane_id() == 0) ws.meta[wid].xo[1] = (uint64_t)h;
     });
 }
 
 // Parallel round r >= 2: a segment whose predecessor's exit (as of round
 // r-1) differs from the entry it was resolved from is resolved again.
-template <bool RAM, bool INV, bool ONE>
+template <bool RAM, bool INV, bool ONE, bool SUCC>
 __global__ __launch_bounds__(kChainThreads) void k_round(Plan P, ChainWs ws, int r) {
     tail_priority();
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(kChainThreads) void k_round(Plan P, ChainWs ws, int
         if (seg > 0) {
             const int64_t X = uni64((int64_t)ws.meta[wid - 1].xo[src]);
             if (X != uni64((int64_t)m.entry))
-                h = resolve_from<RAM, INV>(J, seg, wid, X, false, ws);
+                h = resolve_from<RAM, INV, SUCC>(J, seg, wid, X, false, ws);
         }
         if (lane_id() == 0) m.xo[dst] = (uint64_t)h;
     });
@@ -1394,7 +1395,7 @@ __device__ void settle_job(const JobView& J, const ChainWs& ws, uint64_t* sh,
             uint32_t k2 = uni(flagged[i]);
             int64_t prev = uni64((int64_t)M0[k2 - 1].rexit);
             for (;;) {
-                const int64_t h = resolve_from<RAM, INV>(J, k2, J.item0 + k2, prev,
+                const int64_t h = resolve_from<RAM, INV, RAM>(J, k2, J.item0 + k2, prev,
                                                          false, ws);
                 const uint32_t nxt = k2 + 1;
                 if (nxt >= J.nseg || uni(M0[nxt].claim) == pass ||
@@ -1491,11 +1492,16 @@ __global__ __launch_bounds__(256) void k_emit(Plan P, ChainWs ws) {
         if (MK) (MK)->end(LVL, st);                    \
     } while (0)
 
+// AE's walkers with successor words hold about twice the registers of those
+// without (some 120 against 60), so a launch of many short AE jobs keeps
+// the leaner kernels and no successor pass (`succ` false); RAM always has
+// them.
 template <bool RAM, bool INV, bool ONE>
 static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upper,
                           const uint32_t* n_jobs_d, const ChainWs& ws,
                           hipStream_t st, Marks* mk,
-                          const char* spec_name, const char* idx_name, int part) {
+                          const char* spec_name, const char* idx_name, int part,
+                          bool succ) {
     const dim3 blk(kChainThreads), grid((items_upper + kChainWaves - 1) / kChainWaves);
     const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
     const char* succ_name = RAM ? (ONE ? "successors_ram" : "successors_batch_ram")
@@ -1504,13 +1510,24 @@ static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upp
     if (part & kPartIndex)
         CDC_LAUNCH(mk, 1, idx_name, (k_index<INV, ONE>), dim3(items_upper),
                    dim3(idx_threads<ONE>()), 0, st, P, ws, want);
+    succ = succ || RAM;
     if (part & kPartSpec) {
-        CDC_LAUNCH(mk, 1, succ_name, (k_succ<RAM, ONE>), dim3(items_upper),
-                   dim3(succ_threads<ONE>()), 0, st, P, ws, want);
-        CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+        if (succ)
+            CDC_LAUNCH(mk, 1, succ_name, (k_succ<RAM, ONE>), dim3(items_upper),
+                       dim3(succ_threads<ONE>()), 0, st, P, ws, want);
+        if (succ)
+            CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE, true>), grid, blk, 0, st,
+                       P, ws);
+        else
+            CDC_LAUNCH(mk, 1, spec_name, (k_spec<RAM, INV, ONE, RAM>), grid, blk, 0, st,
+                       P, ws);
     }
-    if (part & kPartFix)
-        CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE>), grid, blk, 0, st, P, ws);
+    if (part & kPartFix) {
+        if (succ)
+            CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE, true>), grid, blk, 0, st, P, ws);
+        else
+            CDC_LAUNCH(mk, 2, "fixup", (k_fix<RAM, INV, ONE, RAM>), grid, blk, 0, st, P, ws);
+    }
     if (part & kPartRest)
         for (int r = 2; r < 2 + kRounds; r++) {
             if (RAM && r == 1 + kRounds && (part & kPartGates))   // entries over runs of one value
@@ -1518,7 +1535,12 @@ static void launch_passes(const Plan& P, uint32_t items_upper, uint32_t jobs_upp
                            dim3(min((jobs_upper + kGateThreads - 1) / kGateThreads, 256u)),
                            dim3(kGateThreads), 0, st, P, jobs_upper, n_jobs_d, ws,
                            (r - 1) & 1);
-            CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE>), grid, blk, 0, st, P, ws, r);
+            if (succ)
+                CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE, true>), grid, blk, 0, st,
+                           P, ws, r);
+            else
+                CDC_LAUNCH(mk, 2, "round", (k_round<RAM, INV, ONE, RAM>), grid, blk, 0, st,
+                           P, ws, r);
         }
 }
 
@@ -1528,13 +1550,14 @@ template <bool RAM, bool INV>
 static void launch_algo(const Plan& P, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
                         const ChainWs& ws, hipStream_t st, Marks* mk,
-                        const char* spec_name, const char* idx_name, int part) {
+                        const char* spec_name, const char* idx_name, int part,
+                        bool ae_succ) {
     if (P.jobs == nullptr)
         launch_passes<RAM, INV, true>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
-                                      spec_name, idx_name, part);
+                                      spec_name, idx_name, part, true);
     else
         launch_passes<RAM, INV, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
-                                       spec_name, idx_name, part);
+                                       spec_name, idx_name, part, ae_succ);
     if (part & kPartRest)
         CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
                    dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
@@ -1543,20 +1566,22 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
 
 hipError_t launch_chain(const Plan& P, uint32_t algo, uint32_t items_upper,
                         uint32_t jobs_upper, const uint32_t* n_jobs_d,
-                        const ChainWs& ws, hipStream_t st, Marks* mk, int part) {
+                        const ChainWs& ws, hipStream_t st, Marks* mk, int part,
+                        bool ae_succ) {
     const bool one = P.jobs == nullptr;
     if (algo == kRam)
         launch_algo<true, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
                                  one ? "speculate_ram" : "speculate_batch_ram",
-                                 one ? "index_ram" : "index_batch_ram", part);
+                                 one ? "index_ram" : "index_batch_ram", part, true);
     else if (algo == kAe)
         launch_algo<false, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
                                   one ? "speculate_ae" : "speculate_batch_ae",
-                                  one ? "index_ae" : "index_batch_ae", part);
+                                  one ? "index_ae" : "index_batch_ae", part, ae_succ);
     else
         launch_algo<false, true>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
                                  one ? "speculate_ae_min" : "speculate_batch_ae_min",
-                                 one ? "index_ae_min" : "index_batch_ae_min", part);
+                                 one ? "index_ae_min" : "index_batch_ae_min", part,
+                                 ae_succ);
     return hipGetLastError();
 }
 
@@ -1575,7 +1600,7 @@ hipError_t launch_ram_ae(const Plan& P, uint32_t items_upper,
     for (uint32_t algo : {kRam, kAe, kAeMin}) {
         if (!one || P.one.algo == algo) {
             const hipError_t e = launch_chain(P, algo, items_upper, jobs_upper,
-                                              n_jobs_d, ws, st, mk, part);
+                                              n_jobs_d, ws, st, mk, part, true);
             if (e != hipSuccess) return e;
         }
     }

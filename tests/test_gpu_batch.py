@@ -166,6 +166,25 @@ def test_batch_many_jobs():
     assert binding.device_errors() == 0
 
 
+def test_batch_many_short_chain_jobs():
+    """9,000 RAM / AE / AE-Min jobs, more chain items than a batch runs AE
+    with successor words for (8,192), so AE and AE-Min take their leaner
+    walkers here, some of them over several segments: every job equals the
+    oracle."""
+    n = 9000
+    host, offs, sizes = make_files(n, 47, max_len=1 << 20)
+    rng = np.random.default_rng(48)
+    algos = [["ram", "ae", "ae_min"][i] for i in rng.integers(0, 3, n)]
+    windows = [ALGO_W[a] for a in algos]
+    assert sum(1 for j in range(n) if algos[j] != "ram" and sizes[j] > 512 << 10) > 0
+    d = torch.from_numpy(host).cuda()
+    b = binding.Batch(d, offs, sizes, algos, windows, 65536)
+    say("case batch many short chain jobs", b.n_jobs, b.total_bytes)
+    b.run()
+    check_batch(b, host, offs, sizes, algos, windows, [65536] * n)
+    assert binding.device_errors() == 0
+
+
 def test_batch_rejects_invalid_jobs():
     host, offs, sizes = make_files(40, 21)
     d = torch.from_numpy(host).cuda()
