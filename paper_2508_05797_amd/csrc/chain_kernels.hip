@@ -1351,7 +1351,7 @@ __global__ __launch_bounds__(kGateThreads) void k_gates(Plan P, uint32_t n_jobs_
 // settles every head, so a job's chain is walked once in order, by as many
 // waves as it has independent stretches.  Then output offsets are
 // assigned.
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool SUCC>
 __device__ void settle_job(const JobView& J, const ChainWs& ws, uint64_t* sh,
                            uint32_t* flagged, uint32_t& n_flagged) {
     const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -1395,7 +1395,7 @@ __device__ void settle_job(const JobView& J, const ChainWs& ws, uint64_t* sh,
             uint32_t k2 = uni(flagged[i]);
             int64_t prev = uni64((int64_t)M0[k2 - 1].rexit);
             for (;;) {
-                const int64_t h = resolve_from<RAM, INV, RAM>(J, k2, J.item0 + k2, prev,
+                const int64_t h = resolve_from<RAM, INV, SUCC>(J, k2, J.item0 + k2, prev,
                                                          false, ws);
                 const uint32_t nxt = k2 + 1;
                 if (nxt >= J.nseg || uni(M0[nxt].claim) == pass ||
@@ -1432,7 +1432,7 @@ __device__ void settle_job(const JobView& J, const ChainWs& ws, uint64_t* sh,
 }
 
 // Settle RAM / AE jobs, one block per job (grid-stride over jobs).
-template <bool RAM, bool INV>
+template <bool RAM, bool INV, bool SUCC>
 __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
                                                  const uint32_t* n_jobs_d,
                                                  ChainWs ws) {
@@ -1445,7 +1445,7 @@ __global__ __launch_bounds__(256) void k_resolve(Plan P, uint32_t n_jobs_h,
         const JobView J = view(P.jobs ? P.jobs[job] : P.one);
         const uint32_t want = RAM ? kRam : (INV ? kAeMin : kAe);
         if (J.ok && J.algo == want && J.n > 0)
-            settle_job<RAM, INV>(J, ws, sh, flagged, n_flagged);
+            settle_job<RAM, INV, SUCC>(J, ws, sh, flagged, n_flagged);
         __syncthreads();
     }
 }
@@ -1558,8 +1558,12 @@ static void launch_algo(const Plan& P, uint32_t items_upper,
     else
         launch_passes<RAM, INV, false>(P, items_upper, jobs_upper, n_jobs_d, ws, st, mk,
                                        spec_name, idx_name, part, ae_succ);
-    if (part & kPartRest)
-        CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV>),
+    if ((part & kPartRest) && (RAM || P.jobs == nullptr || ae_succ))
+        CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV, true>),
+                   dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
+                   n_jobs_d, ws);
+    else if (part & kPartRest)
+        CDC_LAUNCH(mk, 2, "resolve", (k_resolve<RAM, INV, RAM>),
                    dim3(min(jobs_upper, 2048u)), dim3(256), 0, st, P, jobs_upper,
                    n_jobs_d, ws);
 }
