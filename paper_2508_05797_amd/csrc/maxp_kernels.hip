@@ -287,13 +287,48 @@ __device__ void write_forced(uint64_t* out, uint64_t room, int64_t M,
     }
 }
 
+// Inclusive prefix sums of c[0 .. kChainChunk) in place, by the whole block
+// (each thread sums kChainChunk / kChainThreads consecutive counts; a wave
+// scan and the wave totals give each thread its start).
+__device__ void chunk_prefix(uint32_t* c, uint32_t* wsum) {
+    constexpr uint32_t kPer = kChainChunk / kChainThreads;
+    uint32_t v[kPer];
+    const uint32_t t = threadIdx.x, l = lane_id(), wv = t / kWave;
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        v[k] = c[t * kPer + k];
+        sum += v[k];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        inc += l >= d ? o : 0u;
+    }
+    if (l == kWave - 1) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (uint32_t j = 0; j < wv; j++) run += wsum[j];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; k++) {
+        run += v[k];
+        c[t * kPer + k] = run;
+    }
+    __syncthreads();
+}
+
 // All threads of the block call this; the block stages the segments'
 // candidate counts in LDS (one parallel read per kChainChunk segments, zero
-// past the job's last segment) and wave 0 walks them, four segments per
-// lane at a time (the candidates are sparse, so most steps find none).
+// past the job's last segment) and turns them into running totals; wave 0
+// then takes the chunk's candidates 64 at a time in order, each lane finding
+// its candidate's segment by a binary search of the totals (with a few
+// candidates per segment, a step per segment would wait on one list load
+// for each).
 __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                                const uint32_t* cand, uint32_t* err,
-                               uint32_t* lds_nc, ForcedRun* fq, uint32_t& lds_nq) {
+                               uint32_t* lds_nc, uint32_t* wsum, ForcedRun* fq,
+                               uint32_t& lds_nq) {
     const int64_t n = J.n, w = J.w, M = J.M;
     const bool walker = threadIdx.x < kWave;
     uint64_t* out = J.cuts;
@@ -316,37 +351,31 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
         nq++;
         cnt += (uint64_t)t;
     };
-    // the nc candidates of segment seg, in order
-    auto take = [&](uint32_t seg, uint32_t nc) {
-        const uint32_t* list = cand + J.slot0 + (uint64_t)seg * J.cap;
-        const int64_t a = (int64_t)seg * J.seg;
-        for (uint32_t base = 0; base < nc; base += kWave) {
-            const uint32_t k = base + lane_id();
-            const bool valid = k < nc;
-            const int64_t q = valid ? a + (int64_t)list[k] : INT64_MAX;
-            int64_t qprev = __shfl_up(q, 1);
-            uint32_t done = 0;  // lanes below `done` are settled
-            for (;;) {
-                const bool acc = valid && lane_id() >= done && q >= s &&
-                                 ((q - s) % M) >= w;
-                const uint64_t ball = __ballot(acc);
-                if (ball == 0) break;
-                const uint32_t f = (uint32_t)__builtin_ctzll(ball);
-                const int64_t qf = uni64(__shfl(q, (int)f));
-                // accepted run: f, then every next candidate within M+1
-                const bool brk = lane_id() > f &&
-                                 (!valid || (q - qprev - 1) >= M);
-                const uint64_t bb = __ballot(brk);
-                const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
-                forced(s, (qf - s) / M);
-                if (lane_id() >= f && lane_id() < g &&
-                    cnt + (lane_id() - f) < room)
-                    out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
-                cnt += g - f;
-                s = uni64(__shfl(q, (int)(g - 1))) + 1;
-                done = g;
-                if (g >= 64) break;
-            }
+    // the 64 candidates (or fewer: q = INT64_MAX past the last) of one
+    // batch, in order: accepted runs are taken 64 at a time
+    auto take = [&](int64_t q, bool valid) {
+        const int64_t qprev = __shfl_up(q, 1);
+        uint32_t done = 0;  // lanes below `done` are settled
+        for (;;) {
+            const bool acc = valid && lane_id() >= done && q >= s &&
+                             ((q - s) % M) >= w;
+            const uint64_t ball = __ballot(acc);
+            if (ball == 0) break;
+            const uint32_t f = (uint32_t)__builtin_ctzll(ball);
+            const int64_t qf = uni64(__shfl(q, (int)f));
+            // accepted run: f, then every next candidate within M+1
+            const bool brk = lane_id() > f &&
+                             (!valid || (q - qprev - 1) >= M);
+            const uint64_t bb = __ballot(brk);
+            const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
+            forced(s, (qf - s) / M);
+            if (lane_id() >= f && lane_id() < g &&
+                cnt + (lane_id() - f) < room)
+                out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
+            cnt += g - f;
+            s = uni64(__shfl(q, (int)(g - 1))) + 1;
+            done = g;
+            if (g >= 64) break;
         }
     };
     for (uint32_t cb = 0; cb < J.nseg; cb += kChainChunk) {
@@ -361,22 +390,28 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
         for (uint32_t k = 0; k < kChainChunk / kChainThreads; k++)
             lds_nc[threadIdx.x + k * kChainThreads] = v[k];
         __syncthreads();
-        for (uint32_t sb = 0; walker && sb < m; sb += 4 * kWave) {
-            const uint4 q4 = *(const uint4*)&lds_nc[sb + 4 * lane_id()];
-            uint64_t has = __ballot((q4.x | q4.y | q4.z | q4.w) != 0);
-            while (has) {
-                const uint32_t l = (uint32_t)__builtin_ctzll(has);
-                has &= has - 1;
-                const uint32_t seg = cb + sb + 4 * l;
-                const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)q4.x, l);
-                const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)q4.y, l);
-                const uint32_t c2 = (uint32_t)__builtin_amdgcn_readlane((int)q4.z, l);
-                const uint32_t c3 = (uint32_t)__builtin_amdgcn_readlane((int)q4.w, l);
-                if (c0) take(seg, c0);
-                if (c1) take(seg + 1, c1);
-                if (c2) take(seg + 2, c2);
-                if (c3) take(seg + 3, c3);
+        if (m > 1) chunk_prefix(lds_nc, wsum);   // (one segment: its count)
+        // lds_nc[i]: candidates of the chunk's segments 0 .. i (m - 1 holds
+        // the chunk's total, the entries past it repeat it)
+        const uint32_t total = lds_nc[m - 1];
+        for (uint32_t base = 0; walker && base < total; base += kWave) {
+            const uint32_t gi = base + lane_id();
+            const bool valid = gi < total;
+            // the segment k holding candidate gi: the first whose running
+            // total exceeds gi (p: the last one at or below it, -1 if none)
+            int32_t p = -1;
+#pragma unroll
+            for (int32_t step = (int32_t)kChainChunk / 2; step > 0; step >>= 1)
+                if (p + step < (int32_t)m && lds_nc[p + step] <= gi) p += step;
+            const uint32_t k = (uint32_t)(p + 1);
+            int64_t q = INT64_MAX;
+            if (valid) {
+                const uint32_t first = k == 0 ? 0u : lds_nc[k - 1];
+                const uint32_t seg = cb + k;
+                q = (int64_t)seg * J.seg +
+                    (int64_t)cand[J.slot0 + (uint64_t)seg * J.cap + (gi - first)];
             }
+            take(q, valid);
         }
         if (walker && lane_id() == 0) lds_nq = nq;
         __syncthreads();
@@ -407,14 +442,15 @@ __global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n
                                                     const uint32_t* cand,
                                                     uint32_t* err) {
     tail_priority();
-    __shared__ __align__(16) uint32_t nc[kChainChunk];   // read four at a time
+    __shared__ __align__(16) uint32_t nc[kChainChunk];
+    __shared__ uint32_t wsum[kChainThreads / kWave];
     __shared__ ForcedRun fq[kForcedQ];
     __shared__ uint32_t nq;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
         const JobView J = view(P.jobs ? P.jobs[job] : P.one);
         if (!J.ok || J.algo != kMaxp || J.n == 0) continue;   // alike for the block
-        maxp_chain_job(J, meta, cand, err, nc, fq, nq);
+        maxp_chain_job(J, meta, cand, err, nc, wsum, fq, nq);
     }
 }
 
