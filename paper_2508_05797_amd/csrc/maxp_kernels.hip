@@ -357,8 +357,12 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
         const int64_t qprev = __shfl_up(q, 1);
         uint32_t done = 0;  // lanes below `done` are settled
         for (;;) {
-            const bool acc = valid && lane_id() >= done && q >= s &&
-                             ((q - s) % M) >= w;
+            // (the 64-bit remainder and quotient only where q lies M or
+            // more past s: after a content cut the next candidate is
+            // usually within M)
+            const int64_t d = q - s;
+            const bool acc = valid && lane_id() >= done && d >= 0 &&
+                             (d < M ? d : d % M) >= w;
             const uint64_t ball = __ballot(acc);
             if (ball == 0) break;
             const uint32_t f = (uint32_t)__builtin_ctzll(ball);
@@ -368,7 +372,7 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                              (!valid || (q - qprev - 1) >= M);
             const uint64_t bb = __ballot(brk);
             const uint32_t g = bb ? (uint32_t)__builtin_ctzll(bb) : 64u;
-            forced(s, (qf - s) / M);
+            forced(s, qf - s < M ? 0 : (qf - s) / M);
             if (lane_id() >= f && lane_id() < g &&
                 cnt + (lane_id() - f) < room)
                 out[cnt + (lane_id() - f)] = (uint64_t)(q + 1);
