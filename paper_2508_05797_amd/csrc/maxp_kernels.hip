@@ -327,8 +327,8 @@ __device__ void chunk_prefix(uint32_t* c, uint32_t* wsum) {
 // for each).
 __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
                                const uint32_t* cand, uint32_t* err,
-                               uint32_t* lds_nc, uint32_t* wsum, ForcedRun* fq,
-                               uint32_t& lds_nq) {
+                               uint32_t* lds_nc, uint32_t* wsum, int32_t* mk,
+                               ForcedRun* fq, uint32_t& lds_nq) {
     const int64_t n = J.n, w = J.w, M = J.M;
     const bool walker = threadIdx.x < kWave;
     uint64_t* out = J.cuts;
@@ -398,23 +398,54 @@ __device__ void maxp_chain_job(const JobView& J, const SegMeta* meta,
         // lds_nc[i]: candidates of the chunk's segments 0 .. i (m - 1 holds
         // the chunk's total, the entries past it repeat it)
         const uint32_t total = lds_nc[m - 1];
+        uint32_t kc = 0;     // the segment of the batch's first candidate, or before
         for (uint32_t base = 0; walker && base < total; base += kWave) {
-            const uint32_t gi = base + lane_id();
+            const uint32_t l = lane_id(), gi = base + l;
             const bool valid = gi < total;
-            // the segment k holding candidate gi: the first whose running
-            // total exceeds gi (p: the last one at or below it, -1 if none)
-            int32_t p = -1;
+            // segment kc + l: candidates [S, T) of the chunk
+            const uint32_t kl = kc + l;
+            const uint32_t T = kl < m ? lds_nc[kl] : total;
+            const uint32_t S = kl == 0 ? 0u : kl - 1 < m ? lds_nc[kl - 1] : total;
+            const uint32_t end = min(base + (uint32_t)kWave, total);
+            uint32_t k, first;
+            if (end <= (uint32_t)__builtin_amdgcn_readlane((int)T, kWave - 1)) {
+                // the 64 segments from kc hold the batch: each segment that
+                // starts in it marks its first lane, and a lane's segment is
+                // the last mark at or before it (volatile: other lanes write
+                // the slot a lane reads)
+                volatile int32_t* vm = mk;
+                vm[l] = -1;
+                __builtin_amdgcn_wave_barrier();
+                if (T > S && S < end && T > base) vm[S > base ? S - base : 0u] = (int32_t)l;
+                __builtin_amdgcn_wave_barrier();
+                int32_t v = vm[l];
 #pragma unroll
-            for (int32_t step = (int32_t)kChainChunk / 2; step > 0; step >>= 1)
-                if (p + step < (int32_t)m && lds_nc[p + step] <= gi) p += step;
-            const uint32_t k = (uint32_t)(p + 1);
+                for (uint32_t d = 1; d < (uint32_t)kWave; d <<= 1) {
+                    const int32_t o = __shfl_up(v, d);
+                    v = l >= d ? max(v, o) : v;
+                }
+                __builtin_amdgcn_wave_barrier();   // (mk is rewritten next batch)
+                v = max(v, 0);   // (lanes past the last candidate only)
+                k = kc + (uint32_t)v;
+                first = (uint32_t)__shfl((int)S, v);
+            } else {
+                // the segment k holding candidate gi: the first whose
+                // running total exceeds gi (p: the last one at or below it,
+                // -1 if none)
+                int32_t p = -1;
+#pragma unroll
+                for (int32_t step = (int32_t)kChainChunk / 2; step > 0; step >>= 1)
+                    if (p + step < (int32_t)m && lds_nc[p + step] <= gi) p += step;
+                k = (uint32_t)(p + 1);
+                first = k == 0 ? 0u : lds_nc[k - 1];
+            }
             int64_t q = INT64_MAX;
             if (valid) {
-                const uint32_t first = k == 0 ? 0u : lds_nc[k - 1];
                 const uint32_t seg = cb + k;
                 q = (int64_t)seg * J.seg +
                     (int64_t)cand[J.slot0 + (uint64_t)seg * J.cap + (gi - first)];
             }
+            kc = (uint32_t)__builtin_amdgcn_readlane((int)k, kWave - 1);
             take(q, valid);
         }
         if (walker && lane_id() == 0) lds_nq = nq;
@@ -448,13 +479,14 @@ __global__ __launch_bounds__(kChainThreads) void k_maxp_chain(Plan P, uint32_t n
     tail_priority();
     __shared__ __align__(16) uint32_t nc[kChainChunk];
     __shared__ uint32_t wsum[kChainThreads / kWave];
+    __shared__ int32_t mk[kWave];
     __shared__ ForcedRun fq[kForcedQ];
     __shared__ uint32_t nq;
     const uint32_t n_jobs = n_jobs_d ? *n_jobs_d : n_jobs_h;
     for (uint32_t job = blockIdx.x; job < n_jobs; job += gridDim.x) {
         const JobView J = view(P.jobs ? P.jobs[job] : P.one);
         if (!J.ok || J.algo != kMaxp || J.n == 0) continue;   // alike for the block
-        maxp_chain_job(J, meta, cand, err, nc, wsum, fq, nq);
+        maxp_chain_job(J, meta, cand, err, nc, wsum, mk, fq, nq);
     }
 }
 
